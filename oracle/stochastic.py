@@ -1,0 +1,89 @@
+"""Quantum trajectories and quantum state diffusion on an MPS.
+
+Oracle (test infrastructure).  Random numbers are inputs (FP64), so the HIP
+path can be compared draw for draw.
+
+Quantum trajectories, Sec. 4.1 (reading C10): per time step, with the current
+state normalized, the jump probabilities are p_k = gamma_k dt <L_k^+ L_k>
+(eq. TransitionRate times dt).  One uniform u in [0,1) picks jump k if
+sum_{k'<k} p_k' <= u < sum_{k'<=k} p_k'; the jumped state is L_k psi, renormalized.
+If no jump occurs the state is evolved by one Trotter step of exp(-i h^eff dt)
+gates.  Jump XOR evolution, as stated in the paper.
+
+Quantum state diffusion, Sec. 4.2 eqs. (EqMvtStochPsi), (DefAB) and the
+product form that follows them (readings C11, C12): after the h^eff Trotter
+step, apply prod_k (1 + dW_k sqrt(gamma_k) L_k) on the jump sites; no
+renormalization (linear unravelling).  dW_k = sqrt(dt) (x + i y)/sqrt(2) with
+x, y standard normals (complex Gaussian, E|dW|^2 = dt, E dW^2 = 0), or
+dW_k = eta sqrt(dt) with eta = +-1 (the paper's binary noise).
+"""
+import numpy as np
+
+from .measure import jump_expectations
+from .tebd import trotter_step
+
+
+def apply_site_op(state, site, O):
+    """B[a,p,c] -> sum_q O[p,q] B[a,q,c] (operator on the physical index of one site)."""
+    B = state.tensors[site]
+    state.tensors[site] = np.einsum("pq,aqc->apc", O, B)
+
+
+def qt_decide(state, jumps, dt, u):
+    """Return (k or -1, nrm, expectations) for one trajectory, Sec. 4.1."""
+    ops = [(site, op) for site, op, g in jumps]
+    nrm, vals = jump_expectations(state, ops)
+    cum = 0.0
+    for k, (site, op, g) in enumerate(jumps):
+        cum += g * dt * vals[k] / nrm
+        if u < cum:
+            return k, nrm, vals
+    return -1, nrm, vals
+
+
+def qt_jump(state, jumps, dt, u):
+    """Dissipative half of a quantum-trajectory step.  Returns the jump index or -1.
+
+    On a jump the operator is applied and lognorm set so that the state is normalized;
+    otherwise lognorm is set so that the current state is normalized (the evolution
+    that follows starts from a normalized state).
+    """
+    k, nrm, vals = qt_decide(state, jumps, dt, u)
+    if k >= 0:
+        site, op, g = jumps[k]
+        apply_site_op(state, site, op)
+        state.lognorm = -0.5 * np.log(vals[k])
+    else:
+        state.lognorm = -0.5 * np.log(nrm)
+    return k
+
+
+def qt_step(state, model, jumps, dt, u, gate_fn, chi_max, cutoff):
+    k = qt_jump(state, jumps, dt, u)
+    if k < 0:
+        trotter_step(state, gate_fn, 1, dt, chi_max, cutoff)
+    return k
+
+
+def qsd_noise_ops(jumps, dt, rnd_row, noise_kind="gauss"):
+    """Local operators 1 + dW_k sqrt(gamma_k) L_k for one trajectory and one step."""
+    out = []
+    for k, (site, op, g) in enumerate(jumps):
+        if noise_kind == "gauss":
+            x, y = rnd_row[2 * k], rnd_row[2 * k + 1]
+            dW = np.sqrt(dt) * (x + 1j * y) / np.sqrt(2.0)
+        else:
+            eta = -1.0 if rnd_row[k] < 0.5 else 1.0
+            dW = eta * np.sqrt(dt)
+        out.append((site, np.eye(op.shape[0], dtype=np.complex128) + dW * np.sqrt(g) * op))
+    return out
+
+
+def qsd_noise(state, jumps, dt, rnd_row, noise_kind="gauss"):
+    for site, O in qsd_noise_ops(jumps, dt, rnd_row, noise_kind):
+        apply_site_op(state, site, O)
+
+
+def qsd_step(state, jumps, dt, rnd_row, gate_fn, chi_max, cutoff, noise_kind="gauss"):
+    trotter_step(state, gate_fn, 1, dt, chi_max, cutoff)
+    qsd_noise(state, jumps, dt, rnd_row, noise_kind)

@@ -1,0 +1,355 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+integration of the Lindblad equation (ED), the closed-form two-point function,
+special cases with elementary solutions, invariants, Trotter convergence
+orders, and library routines.  CPU only.
+"""
+import numpy as np
+import pytest
+
+from oracle import model as M
+from oracle import exact, ed, dense, tebd, measure, stochastic, kraus
+
+NEEL4 = [1, 0, 1, 0]
+
+
+@pytest.mark.parametrize("occ", [[0, 0, 0, 0], NEEL4, [1, 0, 1, 0, 1]])
+@pytest.mark.parametrize("t", [0.7, 1.3])
+def test_closed_form_matches_exact_lindblad(occ, t):
+    """eq. (SoleqCorr) with K read as in C1 equals exact integration of eq. (Lindblad)."""
+    L = len(occ)
+    rho = ed.evolve_rho(occ, t, J=1.0, gamma=0.5, sink_string=True)
+    C_ed = ed.corr_from_rho(rho, L)
+    C_cf = exact.c_exact(t, occ, J=1.0, gamma=0.5)
+    assert np.max(np.abs(C_ed - C_cf)) < 1e-11
+    assert abs(np.trace(rho) - 1) < 1e-12
+
+
+def test_sink_string_does_not_change_correlations():
+    """Reading C3: dropping the Jordan-Wigner string of L2 leaves C(t) unchanged."""
+    occ = [1, 0, 1, 0]
+    a = ed.corr_from_rho(ed.evolve_rho(occ, 1.1, sink_string=True), 4)
+    b = ed.corr_from_rho(ed.evolve_rho(occ, 1.1, sink_string=False), 4)
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_closed_form_matches_rk4():
+    """Sec. 2.1: the paper integrates eq. (eqCorr) numerically; RK4 converges to the closed form."""
+    occ = [1, 0] * 4
+    C1 = exact.c_exact(2.0, occ)
+    C2 = exact.c_rk4(2.0, occ, 4000)
+    assert np.max(np.abs(C1 - C2)) < 1e-12
+
+
+def test_special_case_no_dissipation():
+    """gamma=0: C(t) = e^{-iJAt} C0 e^{iJAt} (unitary free fermions), checked against ED."""
+    occ = [1, 0, 0, 1]
+    C_ed = ed.corr_from_rho(ed.evolve_rho(occ, 0.9, gamma=0.0), 4)
+    A = np.zeros((4, 4))
+    for i in range(3):
+        A[i, i + 1] = A[i + 1, i] = 1
+    import scipy.linalg as sla
+    U = sla.expm(-1j * A * 0.9)
+    C = U @ np.diag(occ).astype(complex) @ U.conj().T
+    assert np.max(np.abs(C_ed - C)) < 1e-12
+    assert np.max(np.abs(exact.c_exact(0.9, occ, gamma=0.0) - C)) < 1e-12
+
+
+def test_special_case_no_hopping():
+    """J=0: n_1(t) = 1 - (1-n_1(0)) e^{-gamma t}, n_N(t) = n_N(0) e^{-gamma t} (source fills, sink empties)."""
+    g, t = 0.5, 1.7
+    for occ in ([0, 1, 0, 1], [1, 0, 1, 1]):
+        C = exact.c_exact(t, occ, J=0.0, gamma=g)
+        assert abs(C[0, 0].real - (1 - (1 - occ[0]) * np.exp(-g * t))) < 1e-13
+        assert abs(C[3, 3].real - occ[3] * np.exp(-g * t)) < 1e-13
+        C_ed = ed.corr_from_rho(ed.evolve_rho(occ, t, J=0.0, gamma=g), 4)
+        assert np.max(np.abs(C - C_ed)) < 1e-12
+
+
+def test_bond_liouvillians_sum_to_full_generator():
+    """Reading C2: sum_b of the two-site Liouvillians (local index m = n*2+n') is the
+    vectorized generator of eq. (Lindblad), built independently from operator matrices."""
+    for L in (2, 3):
+        mdl = M.Model(L, J=1.0, gamma=0.5)
+        D = 4 ** L
+        tot = np.zeros((D, D), dtype=complex)
+        for b in range(L - 1):
+            lb = mdl.liouvillian_bond(b)
+            left = np.eye(4 ** b)
+            right = np.eye(4 ** (L - b - 2))
+            tot += np.kron(np.kron(left, lb), right)
+        full = ed.liouvillian(L, 1.0, 0.5, sink_string=False).toarray()
+        # full acts on rho_{I,J} -> index I*2^L + J; reorder to sites (n_k n'_k)
+        perm = np.arange(D).reshape((2,) * (2 * L))
+        order = []
+        for k in range(L):
+            order += [k, L + k]
+        perm = perm.transpose(order).reshape(-1)
+        full_sites = full[np.ix_(perm, perm)]
+        assert np.max(np.abs(tot - full_sites)) < 1e-13
+
+
+def test_gate_invariants():
+    mdl = M.Model(6, gamma=0.5)
+    for b in range(5):
+        U = M.gate_unitary(mdl, b, 0.05)
+        assert np.max(np.abs(U.conj().T @ U - np.eye(4))) < 1e-14
+        G = M.gate_liouville(mdl, b, 0.05)
+        # trace preservation: <<1| G = <<1| with <<1|m = delta_{n n'} on both sites
+        t1 = np.zeros(4)
+        t1[0] = t1[3] = 1
+        one = np.kron(t1, t1)
+        assert np.max(np.abs(one @ G - one)) < 1e-14
+        # hermiticity preservation: G maps vec(rho) of a hermitian two-site rho to a hermitian one
+        rng = np.random.default_rng(b)
+        X = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        rho = X @ X.conj().T
+        v = rho.reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(16)
+        w = (G @ v).reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(4, 4)
+        assert np.max(np.abs(w - w.conj().T)) < 1e-13
+    # the non-unitary edge gates shrink norms (contraction), bulk ones don't
+    He = M.gate_heff(mdl, 0, 0.05)
+    assert np.linalg.norm(He, 2) <= 1 + 1e-14
+    assert np.linalg.norm(M.gate_heff(mdl, 2, 0.05) - M.gate_unitary(mdl, 2, 0.05)) < 1e-15
+
+
+def _mpdo_gate_fn(mdl):
+    cache = {}
+
+    def fn(b, tau):
+        key = (b, tau)
+        if key not in cache:
+            cache[key] = M.gate_liouville(mdl, b, tau)
+        return cache[key]
+    return fn
+
+
+def test_tebd_mpdo_equals_dense_trotter_without_truncation():
+    """TEBD machinery (Theta, SVD split, Hastings form, layer schedule) reproduces the exact
+    Trotter product when chi does not bind."""
+    L = 6
+    occ = [1, 0] * 3
+    mdl = M.Model(L)
+    fn = _mpdo_gate_fn(mdl)
+    st = tebd.product_state(occ, "mpdo")
+    for _ in range(6):
+        tebd.trotter_step(st, fn, 2, 0.05, chi_max=4 ** 3, cutoff=0.0)
+    v = dense.trotter_dense(dense.product_vector(occ, 4, "mpdo"), fn, 2, 0.05, 6)
+    vt = tebd.to_dense(st).reshape((4,) * L)
+    assert np.max(np.abs(vt - v)) < 1e-12
+    C, tr = measure.corr_mpdo(st)
+    rho = dense.rho_from_vec(v)
+    C2 = ed.corr_from_rho(rho, L) / np.trace(rho)
+    assert np.max(np.abs(C - C2)) < 1e-12
+    assert abs(tr - 1) < 1e-12
+
+
+def test_tebd_mps_equals_dense_trotter_heff():
+    L = 7
+    occ = [1, 0, 1, 0, 1, 0, 1]
+    mdl = M.Model(L)
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)
+    st = tebd.product_state(occ, "mps")
+    for _ in range(5):
+        tebd.trotter_step(st, fn, 1, 0.1, chi_max=64, cutoff=0.0)
+    v = dense.trotter_dense(dense.product_vector(occ, 2), fn, 1, 0.1, 5)
+    assert np.max(np.abs(tebd.to_dense(st).reshape((2,) * L) - v)) < 1e-12
+    C, n2 = measure.corr_mps(st, normalize=True)
+    psi = v.reshape(-1)
+    assert np.max(np.abs(C - ed.corr_from_psi(psi, L))) < 1e-12
+    assert abs(n2 - np.vdot(psi, psi).real) < 1e-12
+
+
+def test_trotter_orders():
+    """Second-order splitting error falls by ~4 when dt halves, first order by ~2 (Sec. 2.3);
+    the Liouvillian gates keep Tr rho = 1 exactly."""
+    L = 6
+    occ = [1, 0] * 3
+    mdl = M.Model(L)
+    fn = _mpdo_gate_fn(mdl)
+    Cex = exact.c_exact(1.0, occ)
+    errs = {}
+    for order in (1, 2):
+        for dt in (0.1, 0.05):
+            n = int(round(1.0 / dt))
+            v = dense.trotter_dense(dense.product_vector(occ, 4, "mpdo"), fn, order, dt, n)
+            rho = dense.rho_from_vec(v)
+            assert abs(np.trace(rho) - 1) < 1e-13
+            errs[(order, dt)] = np.max(np.abs(ed.corr_from_rho(rho, L) - Cex))
+    r1 = errs[(1, 0.1)] / errs[(1, 0.05)]
+    r2 = errs[(2, 0.1)] / errs[(2, 0.05)]
+    assert 1.7 < r1 < 2.3
+    assert 3.5 < r2 < 4.5
+
+
+def test_discarded_weight_is_hilbert_schmidt_error():
+    """eq. (HilbertSchmidtNorm): the discarded weight equals ||psi - psi_chi||^2 / ||psi||^2."""
+    L = 8
+    occ = [1, 0] * 4
+    mdl = M.Model(L, gamma=0.0)
+    fn = lambda b, tau: M.gate_unitary(mdl, b, tau)
+    st = tebd.product_state(occ, "mps")
+    for _ in range(8):
+        tebd.trotter_step(st, fn, 1, 0.3, chi_max=256, cutoff=0.0)
+    before = tebd.to_dense(st)
+    s2 = st.copy()
+    # centre bond 0 has Lambda_{-1} = 1: truncate it to 1 state
+    w = tebd.two_site_update(s2, 0, np.eye(4, dtype=complex), chi_max=1, cutoff=0.0)
+    after = tebd.to_dense(s2)
+    err = np.vdot(before - after, before - after).real / np.vdot(before, before).real
+    assert w > 1e-4
+    assert abs(err - w) < 1e-12
+
+
+def test_corr_mps_and_mpdo_match_dense_operators():
+    rng = np.random.default_rng(3)
+    L = 5
+    tensors = []
+    dims = [1, 2, 4, 4, 2, 1]
+    for i in range(L):
+        tensors.append(rng.normal(size=(dims[i], 2, dims[i + 1])) + 1j * rng.normal(size=(dims[i], 2, dims[i + 1])))
+    st = tebd.TNState(tensors, [np.ones(d) for d in dims[1:-1]], lognorm=0.3)
+    psi = tebd.to_dense(st)
+    C, n2 = measure.corr_mps(st, normalize=True)
+    assert np.max(np.abs(C - ed.corr_from_psi(psi, L))) < 1e-12
+    Cu, n2u = measure.corr_mps(st, normalize=False)
+    assert np.max(np.abs(Cu - ed.corr_from_psi(psi, L) * np.vdot(psi, psi))) < 1e-10
+    # MPDO of a random (non-hermitian) operator
+    tensors = [rng.normal(size=(dims[i], 4, dims[i + 1])) + 1j * rng.normal(size=(dims[i], 4, dims[i + 1])) for i in range(L)]
+    st = tebd.TNState(tensors, [np.ones(d) for d in dims[1:-1]])
+    v = tebd.to_dense(st).reshape((4,) * L)
+    rho = dense.rho_from_vec(v)
+    C, tr = measure.corr_mpdo(st)
+    assert np.max(np.abs(C - ed.corr_from_rho(rho, L) / np.trace(rho))) < 1e-11
+
+
+def test_purified_measurement_matches_dense():
+    rng = np.random.default_rng(5)
+    L = 4
+    dk = [2, 1, 1, 3]
+    dims = [1, 2, 3, 2, 1]
+    tensors = [rng.normal(size=(dims[i], 2 * dk[i], dims[i + 1])) + 1j * rng.normal(size=(dims[i], 2 * dk[i], dims[i + 1])) for i in range(L)]
+    st = tebd.TNState(tensors, [np.ones(d) for d in dims[1:-1]])
+    # dense X[(n...),(k...)]
+    v = tebd.to_dense(st)  # index (p_0 p_1 ...), p = n*dk + k
+    X = v.reshape([2 * x for x in dk]).reshape(*sum([[2, x] for x in dk], []))
+    perm = [2 * i for i in range(L)] + [2 * i + 1 for i in range(L)]
+    X = X.transpose(perm).reshape(2 ** L, -1)
+    rho = X @ X.conj().T
+    C, n2 = measure.corr_mps(st, normalize=True)
+    assert np.max(np.abs(C - ed.corr_from_rho(rho, L) / np.trace(rho))) < 1e-12
+    assert np.min(np.linalg.eigvalsh(rho)) > -1e-12
+
+
+def test_qt_norm_loss_equals_jump_probability():
+    """eq. (DecroisPsiLindblad): one h^eff step loses norm dt * sum gamma <L^+L> + O(dt^2)."""
+    L = 6
+    mdl = M.Model(L)
+    occ = [1, 0] * 3
+    st = tebd.product_state(occ, "mps")
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)
+    for _ in range(10):
+        tebd.trotter_step(st, fn, 1, 0.05, 64, 0.0)
+    ops = [(s, op) for s, op, g in mdl.jumps]
+    for dt in (0.01, 0.005):
+        s = st.copy()
+        n0 = measure.norm2(s)
+        nrm, vals = measure.jump_expectations(s, ops)
+        p = dt * sum(g * v for (site, op, g), v in zip(mdl.jumps, vals)) / nrm
+        tebd.trotter_step(s, fn, 1, dt, 64, 0.0)
+        loss = 1 - measure.norm2(s) / n0
+        assert abs(loss - p) < 3 * dt ** 2
+
+
+def _traj_average(kind, ntraj, L, T, dt, seed):
+    mdl = M.Model(L)
+    occ = [1, 0] * (L // 2)
+    fn_cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in fn_cache:
+            fn_cache[(b, tau)] = M.gate_heff(mdl, b, tau)
+        return fn_cache[(b, tau)]
+    nsteps = int(round(T / dt))
+    rng = np.random.default_rng(seed)
+    Cs, norms = [], []
+    for _ in range(ntraj):
+        st = tebd.product_state(occ, "mps")
+        if kind == "qt":
+            us = rng.random(nsteps)
+            for k in range(nsteps):
+                stochastic.qt_step(st, mdl, mdl.jumps, dt, us[k], fn, 32, 1e-12)
+            C, n2 = measure.corr_mps(st, normalize=True)
+        else:
+            rn = rng.standard_normal((nsteps, 4))
+            for k in range(nsteps):
+                stochastic.qsd_step(st, mdl.jumps, dt, rn[k], fn, 32, 1e-12)
+            C, n2 = measure.corr_mps(st, normalize=False)
+            norms.append(n2)
+        Cs.append(C)
+    return np.array(Cs), np.array(norms)
+
+
+@pytest.mark.parametrize("kind", ["qt", "qsd"])
+def test_trajectory_average_matches_exact_within_clt(kind):
+    """Sec. 4: the trajectory average reproduces the Lindblad dynamics; error bar eq. (ErrorCLT)."""
+    L, T, dt, ntraj = 4, 1.0, 0.01, 200
+    Cs, norms = _traj_average(kind, ntraj, L, T, dt, seed=11)
+    Cex = exact.c_exact(T, [1, 0] * (L // 2))
+    n = np.real(np.einsum("tii->ti", Cs))
+    mean = n.mean(0)
+    err = n.std(0, ddof=1) / np.sqrt(ntraj)
+    ne = np.real(np.diag(Cex))
+    # 4 sigma plus the O(dt) splitting bias
+    assert np.all(np.abs(mean - ne) < 4 * err + 0.02)
+    if kind == "qsd":
+        # mean norm is conserved (Sec. 4.2)
+        assert abs(norms.mean() - 1) < 4 * norms.std(ddof=1) / np.sqrt(ntraj) + 0.02
+
+
+def test_kraus_thin_route_equals_full_diagonalization():
+    """Reading C9: the 2chi_k x 2chi_k route gives the same sum_k A A^+ as diagonalizing R."""
+    rng = np.random.default_rng(7)
+    for dk in (1, 2, 4):
+        A = rng.normal(size=(3, 2 * dk, 5)) + 1j * rng.normal(size=(3, 2 * dk, 5))
+        lam = np.array([0.8, 0.5, 0.33])
+        for Lop in (M.SP, M.SM):
+            a = kraus.kraus_thin(A, dk, Lop, 0.5, 0.02, 4, lam)
+            b = kraus.kraus_full(A, dk, Lop, 0.5, 0.02, 4, lam)
+            ra, rb = kraus.local_rho_block(a, 4, lam), kraus.local_rho_block(b, 4, lam)
+            assert np.max(np.abs(ra - rb)) < 1e-12
+            a = kraus.kraus_thin(A, dk, Lop, 0.5, 0.02, 4)
+            ra = kraus.local_rho_block(a, 4)
+            # with chi_k >= 2 dk nothing is discarded: the block equals A A^+ + gamma dt (LA)(LA)^+
+            if 2 * dk <= 4:
+                A4 = A.reshape(3, 2, dk, 5)
+                LA = np.einsum("nm,amkc->ankc", Lop, A4)
+                def blk(T):
+                    return T.transpose(0, 1, 3, 2).reshape(3 * 2 * 5, dk)
+                want = blk(A4) @ blk(A4).conj().T + 0.5 * 0.02 * blk(LA) @ blk(LA).conj().T
+                assert np.max(np.abs(ra - want)) < 1e-12
+
+
+def test_purified_evolution_is_positive_and_close_to_exact():
+    """Sec. 3.2: rho = XX^+ stays positive; first-order splitting converges to the exact C(t)."""
+    L = 4
+    occ = [1, 0, 1, 0]
+    mdl = M.Model(L)
+    chik = 4
+    dks = [chik if i in (0, L - 1) else 1 for i in range(L)]
+    T = 1.0
+    errs = []
+    for dt in (0.02, 0.01):
+        st = tebd.product_state(occ, "purified", dk=dks)
+        g4 = {}
+        for _ in range(int(round(T / dt))):
+            for parity, tau in M.trotter_layers(1, dt):
+                for b in M.layer_bonds(L, parity):
+                    G = M.purified_gate(M.gate_heff(mdl, b, tau), dks[b], dks[b + 1])
+                    tebd.two_site_update(st, b, G, 64, 0.0)
+            kraus.kraus_step(st, mdl.jumps, dt, chik)
+        C, tr = measure.corr_mps(st, normalize=True)
+        errs.append(np.max(np.abs(C - exact.c_exact(T, occ))))
+    assert errs[1] < 0.6 * errs[0]
+    assert errs[1] < 0.05

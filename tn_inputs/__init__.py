@@ -1,0 +1,58 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the HIP-side tests/bench.
+
+Holds none of the method's arithmetic: only random streams (PCG64) and the
+construction of random right-isometric site tensors with prescribed bond
+weights, used as pre-evolved stand-ins for saturated trajectory states.
+"""
+import numpy as np
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniforms(seed, shape):
+    """FP64 uniforms in [0, 1): quantum-jump draws, one per trajectory per step."""
+    return rng(seed).random(shape)
+
+
+def normals(seed, shape):
+    """FP64 standard normals: real and imaginary parts of Wiener increments."""
+    return rng(seed).standard_normal(shape)
+
+
+def neel(L):
+    """Neel occupation pattern, first site occupied: 1,0,1,0,..."""
+    return [1 - (i % 2) for i in range(L)]
+
+
+def bond_dims(L, chi, d=2):
+    """Largest bond dimensions an open chain of L sites with local dimension d allows, capped at chi."""
+    dims = [1]
+    for b in range(1, L):
+        dims.append(int(min(chi, d ** min(b, L - b))))
+    dims.append(1)
+    return dims
+
+
+def random_isometric_mps(seed, L, chi, d=2, decay=8.0):
+    """Random MPS in right-isometric (Hastings) form with geometric bond weights.
+
+    Site tensors B_i[a, p, c] with sum_{p,c} B B^+ = 1 on the left index; bond weights
+    Lambda_b[a] proportional to exp(-a/decay), normalized to sum Lambda^2 = 1.
+    Returns (tensors, lams, dims).
+    """
+    g = rng(seed)
+    dims = bond_dims(L, chi, d)
+    tensors = []
+    for i in range(L):
+        cl, cr = dims[i], dims[i + 1]
+        X = g.standard_normal((d * cr, cl)) + 1j * g.standard_normal((d * cr, cl))
+        Q, _ = np.linalg.qr(X)           # (d cr) x cl with orthonormal columns
+        B = Q.conj().T.reshape(cl, d, cr)
+        tensors.append(B)
+    lams = []
+    for b in range(L - 1):
+        lam = np.exp(-np.arange(dims[b + 1]) / decay)
+        lams.append(lam / np.sqrt(np.sum(lam ** 2)))
+    return tensors, lams, dims
