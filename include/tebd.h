@@ -1,0 +1,179 @@
+/*
+ * tebd.h -- C ABI of the MI355X (gfx950) batched TEBD-Lindblad hot path.
+ *
+ * Method: C. Chatelain, "A first introduction to Matrix Product State
+ * algorithms for the integration of Lindblad equation".  The library evolves
+ * a batch of B independent instances of one of three tensor-network forms of
+ * an open chain of L sites:
+ *   TN_KIND_MPS       pure states (quantum trajectories, Sec. 4.1; quantum state
+ *                     diffusion, Sec. 4.2; unitary TEBD, Sec. 2.3), local dim 2;
+ *   TN_KIND_MPDO      vectorized density matrix, local index m = n*2 + n'
+ *                     (Sec. 3.1, eq. Choi / eq. MPDO), local dim 4;
+ *   TN_KIND_PURIFIED  locally purified rho = X X^+ (Sec. 3.2, eq. Purified1), local
+ *                     index p = n*chi_k + k; Kraus index only on jump sites.
+ * Every instance is stored in Hastings form: psi = exp(lognorm) B_0 ... B_{L-1}
+ * with site tensors B_i[a][p][c] (row-major, compact chi_l x d_i x chi_r) and
+ * FP64 bond weights Lambda_b (bond b joins sites b and b+1, 0-based).
+ *
+ * Conventions shared by all entry points
+ *   - Complex numbers cross the boundary as interleaved (re, im) doubles.
+ *   - Host pointers are borrowed for the duration of the call and never retained.
+ *   - The device arena is owned by the caller (e.g. a torch uint8 tensor); the
+ *     library sub-allocates it and never frees it.  It must stay alive and
+ *     unmoved until mps_free.
+ *   - All device work is ordered on the HIP stream given to mps_alloc.  Entry
+ *     points that return host outputs synchronize that stream before returning.
+ *   - Return value 0 on success or a negative TN_E* code; mps_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - A handle must not be used by two host threads at once.
+ */
+#ifndef TEBD_H
+#define TEBD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TN_OK        0
+#define TN_EINVAL   -1   /* null pointer, bad size or shape, unsupported option */
+#define TN_ENOMEM   -2   /* arena too small */
+#define TN_EHIP     -3   /* a HIP runtime call failed */
+#define TN_ENOCONV  -4   /* an eigensolver did not converge; results are still written */
+#define TN_ENUMERIC -5   /* NaN/Inf detected in a result */
+
+#define TN_KIND_MPS      0
+#define TN_KIND_MPDO     1
+#define TN_KIND_PURIFIED 2
+
+#define TN_FP64  0   /* all contractions and storage in complex128 */
+#define TN_SPLIT 1   /* complex64 storage and MFMA contractions (FP32 accumulate);
+                        Gram, eigensolver, weights, norms and log-norms in FP64 */
+
+#define TN_MODE_QT    0  /* quantum-trajectory jumps, Sec. 4.1 */
+#define TN_MODE_QSD   1  /* quantum-state-diffusion noise, Sec. 4.2 */
+#define TN_MODE_KRAUS 2  /* Kraus-index compression of the purified form, Sec. 3.2 */
+
+#define TN_NOISE_GAUSS  0  /* dW = sqrt(dt) (x + i y)/sqrt(2), x, y ~ N(0,1) */
+#define TN_NOISE_BINARY 1  /* dW = eta sqrt(dt), eta = -1 if u < 1/2 else +1 (the paper's choice) */
+
+/* Model of Sec. 2.1: H = sum_b h_b with two-site terms h_b on sites (b, b+1),
+ * and local jump operators L_k on site jump_site[k] with rate gamma[k]
+ * (Sec. 1 eq. Lindblad; eq. LindbladLocal for how their -i/2 gamma L^+L parts are
+ * shared between bonds). */
+typedef struct tn_model {
+    int L;                    /* number of sites, >= 2 */
+    int d;                    /* local Hilbert dimension; must be 2 */
+    const double* h_bond;     /* (L-1) * 16 complex: 4x4 [out, in] in the basis n_b*2 + n_{b+1} */
+    int n_jumps;              /* 0 .. 8 */
+    const int* jump_site;     /* n_jumps sites, 0-based */
+    const double* jump_op;    /* n_jumps * 4 complex: 2x2 [out, in] local operator (no string) */
+    const double* gamma;      /* n_jumps rates >= 0 */
+} tn_model;
+
+/* Bytes of device arena needed for a state of the given shape plus the
+ * workspace of one chunk of chunk_items two-site updates (chunk_items <= 0:
+ * the library's default).  Returns 0 on invalid arguments. */
+size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int chi_k_max,
+                       int precision, int chunk_items);
+
+/* Create `batch` instances of the product state init_occ (L ints in {0,1}); all
+ * bond dimensions 1.  MPDO: rho = |occ><occ|.  PURIFIED: X = |occ> with a Kraus
+ * index of dimension chi_k_max on every jump site (unused columns zero).
+ * chi_max >= 1 caps every bond dimension.  sv_cutoff: singular values
+ * sigma_a <= sv_cutoff * sigma_0 are discarded (Sec. 2.2 truncation).
+ * arena: device pointer, arena_bytes >= mps_arena_bytes(...).  hip_stream: a
+ * hipStream_t (NULL = default stream).  On success *out is a new handle. */
+int mps_alloc(void** out, int kind, const tn_model* model, int batch, int chi_max,
+              int chi_k_max, int precision, const int* init_occ, double sv_cutoff,
+              void* arena, size_t arena_bytes, void* hip_stream);
+
+/* Apply n_steps Trotter steps of size dt (Sec. 2.3; order 1: odd bonds then
+ * even bonds; order 2: even dt/2, odd dt, even dt/2; bonds named by their
+ * 1-based left site).  Gates are built in FP64 on the host: exp(-i h^eff_b tau)
+ * for MPS and PURIFIED (h^eff: eq. EffHamiltonian shared per eq. LindbladLocal;
+ * identity on Kraus indices), exp(l_b tau) for MPDO (eq. Liouvillian, row-major
+ * vectorization).  Each two-site update forms Theta (eq. Theta / ThetaPurified),
+ * splits it by a truncated FP64 SVD and stores it back in Hastings form; the
+ * discarded weight (eq. HilbertSchmidtNorm) is accumulated per instance.
+ * mask: B bytes or NULL; instances with mask[b] != 0 are not evolved.
+ * trunc_weight_out: B doubles or NULL, receives the accumulated discarded weight. */
+int tebd_step(void* s, double dt, int order, int n_steps, const unsigned char* mask,
+              double* trunc_weight_out);
+
+/* Dissipative part of one time step, on every instance.
+ * TN_MODE_QT (MPS): rates p_k = gamma_k dt <L_k^+L_k>/<psi|psi> (eq. TransitionRate);
+ *   rnd = B uniforms; jump k where sum_{k'<k} p_k' <= u < sum_{k'<=k} p_k'; the jumped
+ *   state is L_k psi.  lognorm is reset so that the state is normalized.
+ *   jumped_out[b] = k or -1, mask_out[b] = (k >= 0) (both B, may be NULL).
+ * TN_MODE_QSD (MPS): psi <- prod_k (1 + dW_k sqrt(gamma_k) L_k) psi (Sec. 4.2), no
+ *   renormalization.  rnd = B*n_jumps*2 normals (GAUSS) or B*n_jumps uniforms (BINARY).
+ * TN_MODE_KRAUS (PURIFIED): on each jump site, rho -> rho + gamma dt L rho L^+ then the
+ *   Kraus index is compressed back to chi_k_max (eq. MatrixR, eq. NewPurified); rnd NULL. */
+int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
+                int* jumped_out, unsigned char* mask_out);
+
+/* Correlation matrix C_ij = <c_i^+ c_j> (Sec. 2.1) with the Jordan-Wigner string,
+ * by exact contraction of each instance.
+ * normalize (MPS): 1 -> <psi|O|psi>/<psi|psi>; 0 -> <psi|O|psi> (linear QSD estimator).
+ * MPDO: Tr(rho O)/Tr rho; PURIFIED: Tr(X X^+ O)/Tr(X X^+) (normalize ignored).
+ * C_mean: L*L complex, batch mean (row i = c_i^+).  C_var: L*L doubles or NULL, batch
+ * variance E|C - mean|^2.  C_each: B*L*L complex or NULL.  norm_out: B doubles or
+ * NULL: <psi|psi> (MPS, PURIFIED) or Tr rho (MPDO), including exp(lognorm). */
+int measure_corr(void* s, int normalize, double* C_mean, double* C_var, double* C_each,
+                 double* norm_out);
+
+/* Release the handle (not the arena). */
+int mps_free(void* s);
+
+/* Thread-local description of the last error ("" if none). */
+const char* mps_last_error(void);
+
+/* ---- state I/O: checkpoint / resume and test injection ------------------- */
+
+/* Capacity (in complex numbers) of the tensor buffer of one instance, and in
+ * doubles of its bond-weight buffer. */
+size_t mps_instance_tensor_capacity(const void* s);
+size_t mps_instance_lambda_capacity(const void* s);
+
+/* Read instance `inst`: dims (L+1 ints, dims[0] = dims[L] = 1), tensors packed
+ * site after site (chi_l*d_i*chi_r complex each), lambdas packed bond after bond
+ * (dims[b+1] doubles each), lognorm and accumulated truncation weight. */
+int mps_get_instance(const void* s, int inst, int* dims, double* tensors, double* lambdas,
+                     double* lognorm, double* trunc);
+
+/* Overwrite instance `inst` with the same packed layout as mps_get_instance. */
+int mps_set_instance(void* s, int inst, const int* dims, const double* tensors,
+                     const double* lambdas, double lognorm);
+
+/* Copy instance src over every other instance (device to device). */
+int mps_replicate(void* s, int src);
+
+/* ---- host-side gate builder (no device work) ----------------------------- */
+
+/* Gate of bond b for time tau, as used by tebd_step: 4x4 exp(-i h^eff_b tau) for
+ * kind MPS / PURIFIED (before embedding), 16x16 exp(l_b tau) for MPDO in the
+ * basis (m_b, m_{b+1}).  out: 16 or 256 complex. */
+int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
+
+/* ---- kernel timing (HIP events on the library stream) -------------------- */
+#define TN_K_THETA   0  /* Theta formation + gate */
+#define TN_K_GRAM    1  /* weighted Gram matrix */
+#define TN_K_HETRD   2  /* Householder tridiagonalization */
+#define TN_K_STEQR   3  /* tridiagonal QL eigenvalues */
+#define TN_K_VECS    4  /* eigenvectors: rotations + back-transformation */
+#define TN_K_SPLIT   5  /* split / store */
+#define TN_K_MEASURE 6  /* measurement sweep */
+#define TN_K_JUMPS   7  /* dissipative step */
+#define TN_K_COUNT   8
+
+/* Enable (1) or disable (0) per-kernel event timing; enabling resets the totals. */
+int tn_prof_enable(void* s, int on);
+/* Total milliseconds and launch count recorded for a kernel id since enabling. */
+int tn_prof_query(void* s, int kernel_id, double* total_ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEBD_H */

@@ -1,0 +1,586 @@
+// Two-site TEBD update kernels (gfx950).
+//
+// One Trotter layer is a set of independent work items (instance b, bond) --
+// all bonds of one parity of every unmasked instance commute (Sec. 2.3).  Each
+// item goes through
+//   k_theta   M = B_bond . B_{bond+1}               (complex GEMM, eq. Theta)
+//   k_gate    Theta~ = G (x) M on the physical pair  (eq. Theta / eq. ThetaPurified)
+//   k_gram    H = Theta~^+ diag(Lambda_{bond-1}^2) Theta~   (FP64, lower triangle)
+//   k_hetrd   Householder reduction H = Q T Q^+, T real tridiagonal (FP64)
+//   k_steqr   implicit QL on T, logging every Givens rotation (FP64)
+//   k_select  sort eigenvalues, truncation rank, discarded weight (eq. HilbertSchmidtNorm)
+//   k_vecs    replay the rotations on the selected unit vectors, back-transform by Q,
+//             store B_{bond+1} <- V^+ (right isometry)
+//   k_split   B_bond <- Theta~ V / s  (Hastings split), dims, log s and weight per item
+// The eigenvalues of H are the squared singular values of Theta = Lambda Theta~ and
+// its eigenvectors the right singular vectors, so this is the truncated SVD of the
+// two-site update computed in FP64 without ever forming U.
+#include "common.h"
+#include "gemm.h"
+#include <float.h>
+
+#define NT 256
+
+__device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1)) / 2 + c; }
+
+struct ItemDims { int b, bond, chil, chim, chir, dl, dr, m, n; };
+
+__device__ __forceinline__ bool item_dims(const DevState& s, const DevWork& w, int j, ItemDims& d) {
+    if (j >= w.nitems) return false;
+    if (!item_coords(w, j, d.b, d.bond)) return false;
+    d.chil = bond_dim(s, d.b, d.bond);
+    d.chim = bond_dim(s, d.b, d.bond + 1);
+    d.chir = bond_dim(s, d.b, d.bond + 2);
+    d.dl = s.dsite[d.bond];
+    d.dr = s.dsite[d.bond + 1];
+    d.m = d.chil * d.dl;
+    d.n = d.dr * d.chir;
+    return true;
+}
+
+// ------------------------------------------------------------------ Theta
+template <class T>
+__global__ __launch_bounds__(NT) void k_theta(DevState s, DevWork w, int tiles_n) {
+    __shared__ T As[8 * 64], Bs[8 * 64];
+    ItemDims d;
+    if (!item_dims(s, w, blockIdx.y, d)) return;
+    int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= d.m || tn * 64 >= d.n) return;
+    const T* P = site_ptr<T>(s, d.b, d.bond);
+    const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
+    T* out = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    const int K = d.chim, n = d.n;
+    block_gemm<T, true, true, 8>(
+        d.m, d.n, K, tm * 64, tn * 64,
+        [&](int r, int k) { return P[(size_t)r * K + k]; },
+        [&](int k, int c) { return Q[(size_t)k * n + c]; },
+        [&](int r, int c, T v) { out[(size_t)r * n + c] = v; }, As, Bs);
+}
+
+// ------------------------------------------------------------------ gate on the physical pair
+template <class T>
+__global__ __launch_bounds__(NT) void k_gate(DevState s, DevWork w) {
+    typedef typename real_of<T>::type R;
+    __shared__ T G[256];
+    ItemDims d;
+    if (!item_dims(s, w, blockIdx.y, d)) return;
+    const int D = d.dl * d.dr;
+    const double2* g = w.gates + (size_t)d.bond * w.gstride;
+    for (int e = threadIdx.x; e < D * D; e += NT) G[e] = cconv<T>(g[e]);
+    __syncthreads();
+    T* th = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    const int n = d.n, chir = d.chir, dl = d.dl, dr = d.dr;
+    for (int idx = blockIdx.x * NT + threadIdx.x; idx < d.chil * chir; idx += gridDim.x * NT) {
+        int a = idx / chir, c = idx % chir;
+        T v[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            if (e < D) {
+                int p = e / dr, q = e % dr;
+                v[e] = th[(size_t)(a * dl + p) * n + q * chir + c];
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 16; ++o) {
+            if (o < D) {
+                T acc = czero<T>();
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (e < D) cfma(acc, G[o * D + e], v[e]);
+                int p = o / dr, q = o % dr;
+                th[(size_t)(a * dl + p) * n + q * chir + c] = acc;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weighted Gram (FP64)
+template <class T>
+__global__ __launch_bounds__(NT) void k_gram(DevState s, DevWork w, int tiles_n) {
+    __shared__ double2 As[8 * 64], Bs[8 * 64];
+    ItemDims d;
+    if (!item_dims(s, w, blockIdx.y, d)) return;
+    int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= d.n || tn * 64 >= d.n || tm < tn) return;  // lower block triangle only
+    const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    const int n = d.n, dl = d.dl;
+    double2* G = w.gram + (size_t)blockIdx.y * w.nmax * w.nmax;
+    block_gemm<double2, false, true, 8>(
+        n, n, d.m, tm * 64, tn * 64,
+        [&](int i, int r) { return cconj(cconv<double2>(th[(size_t)r * n + i])); },
+        [&](int r, int c) {
+            double wl = 1.0;
+            if (lamL) { double l = lamL[r / dl]; wl = l * l; }
+            return cscale(cconv<double2>(th[(size_t)r * n + c]), wl);
+        },
+        [&](int i, int c, double2 v) { G[(size_t)i * n + c] = v; }, As, Bs);
+}
+
+// ------------------------------------------------------------------ Householder tridiagonalization
+// LAPACK-style lower reduction (reflector H_i = I - tau_i v_i v_i^+, v_i[0] = 1, acting on
+// rows i+1..n-1); the off-diagonal of T is made real by the reflector choice, so T is a real
+// symmetric tridiagonal matrix (d, e) and H = Q T Q^+ with Q = H_0 H_1 ... H_{n-2}.
+#define HETRD_LDS_N 128
+template <bool LDS>
+__global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
+    __shared__ double2 packed_lds[LDS ? (HETRD_LDS_N * (HETRD_LDS_N + 1) / 2) : 1];
+    __shared__ double2 vv[512], pp[512];
+    __shared__ double red[NT];
+    __shared__ double2 redc[NT];
+    __shared__ double2 sh_tau, sh_scal, sh_alpha2;
+    __shared__ double sh_beta;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = d.n, tid = threadIdx.x;
+    double2* A = LDS ? packed_lds : (w.pscratch + (size_t)j * (w.nmax * (w.nmax + 1) / 2));
+    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+    double* dd = w.dd + (size_t)j * w.nmax;
+    double* ee = w.ee + (size_t)j * w.nmax;
+    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    double2* tau = w.tau + (size_t)j * w.nmax;
+
+    for (int e = tid; e < n * n; e += NT) {
+        int r = e / n, c = e % n;
+        if (c <= r) A[tri(r, c)] = G[e];
+    }
+    __syncthreads();
+
+    for (int i = 0; i + 1 < n; ++i) {
+        const int len = n - 1 - i;  // length of the reflector
+        // ||x||^2 with x = A[i+2 .., i]
+        double part = 0.0;
+        for (int r = i + 2 + tid; r < n; r += NT) {
+            double2 x = A[tri(r, i)];
+            part += x.x * x.x + x.y * x.y;
+        }
+        red[tid] = part;
+        __syncthreads();
+        for (int o = NT / 2; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            double xn2 = red[0];
+            double2 alpha = A[tri(i + 1, i)];
+            double2 t, sc;
+            double beta;
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                t = mk(0.0, 0.0);
+                beta = alpha.x;
+                sc = mk(1.0, 0.0);
+            } else {
+                double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                t = mk((beta - alpha.x) / beta, -alpha.y / beta);
+                double2 z = mk(alpha.x - beta, alpha.y);  // scal = 1 / z
+                double den = z.x * z.x + z.y * z.y;
+                sc = mk(z.x / den, -z.y / den);
+            }
+            sh_tau = t;
+            sh_scal = sc;
+            sh_beta = beta;
+            dd[i] = A[tri(i, i)].x;
+            ee[i] = beta;
+            tau[i] = t;
+        }
+        __syncthreads();
+        const double2 t = sh_tau, sc = sh_scal;
+        for (int r = tid; r < len; r += NT) {
+            double2 v = (r == 0) ? mk(1.0, 0.0) : cmul(A[tri(i + 1 + r, i)], sc);
+            vv[r] = v;
+            refl[(size_t)i * w.nmax + r] = v;
+        }
+        __syncthreads();
+        if (t.x != 0.0 || t.y != 0.0) {
+            // p = tau * A22 v  (two threads per row)
+            for (int rr = (tid >> 1); rr < len; rr += NT / 2) {
+                const int half = tid & 1;
+                const int c0 = half ? len / 2 : 0, c1 = half ? len : len / 2;
+                const int R = i + 1 + rr;
+                double2 acc = mk(0.0, 0.0);
+                for (int cc = c0; cc < c1; ++cc) {
+                    const int C = i + 1 + cc;
+                    double2 a = (cc <= rr) ? A[tri(R, C)] : cconj(A[tri(C, R)]);
+                    cfma(acc, a, vv[cc]);
+                }
+                double ox = __shfl_xor(acc.x, 1), oy = __shfl_xor(acc.y, 1);
+                acc.x += ox;
+                acc.y += oy;
+                if (!half) pp[rr] = cmul(t, acc);
+            }
+            __syncthreads();
+            // alpha2 = -1/2 tau (p^+ v)
+            double2 part2 = mk(0.0, 0.0);
+            for (int r = tid; r < len; r += NT) cfmac(part2, pp[r], vv[r]);
+            redc[tid] = part2;
+            __syncthreads();
+            for (int o = NT / 2; o > 0; o >>= 1) {
+                if (tid < o) redc[tid] = cadd(redc[tid], redc[tid + o]);
+                __syncthreads();
+            }
+            if (tid == 0) {
+                double2 a2 = cmul(t, redc[0]);
+                sh_alpha2 = mk(-0.5 * a2.x, -0.5 * a2.y);
+            }
+            __syncthreads();
+            const double2 a2 = sh_alpha2;
+            for (int r = tid; r < len; r += NT) {
+                double2 p = pp[r];
+                cfma(p, a2, vv[r]);
+                pp[r] = p;  // w
+            }
+            __syncthreads();
+            // A22 -= v w^+ + w v^+ (lower triangle)
+            for (int e = tid; e < len * len; e += NT) {
+                int rr = e / len, cc = e % len;
+                if (cc <= rr) {
+                    double2 a = A[tri(i + 1 + rr, i + 1 + cc)];
+                    double2 u1 = cmulc(pp[cc], vv[rr]);  // v_r conj(w_c)
+                    double2 u2 = cmulc(vv[cc], pp[rr]);  // w_r conj(v_c)
+                    a.x -= u1.x + u2.x;
+                    a.y -= u1.y + u2.y;
+                    A[tri(i + 1 + rr, i + 1 + cc)] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        dd[n - 1] = A[tri(n - 1, n - 1)].x;
+        ee[n - 1] = 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ implicit QL with rotation log
+// Tridiagonal QL with implicit Wilkinson-type shifts (one thread per item).  Every
+// Givens rotation (i, c, s) is logged; the eigenvector matrix is the ordered product
+// Z = G_1 G_2 ... G_N with G acting on columns (i, i+1) as
+//   Z[:,i] <- c Z[:,i] - s Z[:,i+1],  Z[:,i+1] <- s Z[:,i] + c Z[:,i+1].
+__global__ __launch_bounds__(64) void k_steqr(DevState s, DevWork w) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    ItemDims dm;
+    if (!item_dims(s, w, j, dm)) return;
+    const int n = dm.n;
+    double* d = w.dd + (size_t)j * w.nmax;
+    double* e = w.ee + (size_t)j * w.nmax;
+    int* li = w.logi + (size_t)j * w.logcap;
+    double2* lcs = w.logcs + (size_t)j * w.logcap;
+    const int cap = w.logcap;
+    int nr = 0, flag = 0;
+    e[n - 1] = 0.0;
+    // absolute deflation floor eps*||T||: the Gram matrix fixes its eigenvalues only to that accuracy,
+    // and it lets exactly-zero blocks (product states) deflate at once
+    double tnorm = 0.0;
+    for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+    const double afloor = DBL_EPSILON * tnorm;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        while (true) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                double ddm = fabs(d[m]) + fabs(d[m + 1]);
+                if (fabs(e[m]) <= DBL_EPSILON * ddm || fabs(e[m]) <= afloor) break;
+            }
+            if (m == l) break;
+            if (iter++ >= 60) { flag |= TN_FLAG_NOCONV; break; }
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+            double sn = 1.0, c = 1.0, p = 0.0;
+            bool early = false;
+            for (int i = m - 1; i >= l; --i) {
+                double f = sn * e[i], bb = c * e[i];
+                r = hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    early = true;
+                    break;
+                }
+                sn = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * sn + 2.0 * c * bb;
+                p = sn * r;
+                d[i + 1] = g + p;
+                g = c * r - bb;
+                if (nr < cap) {
+                    li[nr] = i;
+                    lcs[nr] = mk(c, sn);
+                } else {
+                    flag |= TN_FLAG_LOGFULL;
+                }
+                ++nr;
+            }
+            if (early) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    w.nrot[j] = nr < cap ? nr : cap;
+    if (flag) atomicOr(w.flags, flag);
+}
+
+// ------------------------------------------------------------------ selection and truncation
+__global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
+    __shared__ double lamv[512];
+    __shared__ double red[NT];
+    __shared__ int redi[NT];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = d.n, tid = threadIdx.x;
+    const double* ev = w.dd + (size_t)j * w.nmax;
+    for (int i = tid; i < n; i += NT) lamv[i] = ev[i];
+    __syncthreads();
+    // max and total (fixed reduction order: deterministic)
+    double mx = -1e300, tot = 0.0;
+    for (int i = tid; i < n; i += NT) { mx = fmax(mx, lamv[i]); tot += lamv[i]; }
+    red[tid] = mx;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) { if (tid < o) red[tid] = fmax(red[tid], red[tid + o]); __syncthreads(); }
+    const double lmax = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) { if (tid < o) red[tid] += red[tid + o]; __syncthreads(); }
+    const double total = red[0];
+    __syncthreads();
+    // The Gram route resolves eigenvalues only to ~DBL_EPSILON * lmax (singular values to ~1e-8 sigma_0):
+    // a cutoff below that floor cannot be applied faithfully, so every direction is kept (up to chi);
+    // discarding a noise-level direction would change the state by up to ~1e-8.
+    const double thr = (s.cutoff2 < 1e-14) ? -1e300 : s.cutoff2 * lmax;
+    int cnt = 0;
+    for (int i = tid; i < n; i += NT) cnt += (lamv[i] > thr) ? 1 : 0;
+    redi[tid] = cnt;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) { if (tid < o) redi[tid] += redi[tid + o]; __syncthreads(); }
+    int k = redi[0];
+    k = k < s.chi ? k : s.chi;
+    k = k < d.m ? k : d.m;
+    k = k < n ? k : n;
+    if (k < 1) k = 1;
+    int* sel = w.sel + (size_t)j * w.nmax;
+    double kept_part = 0.0;
+    for (int i = tid; i < n; i += NT) {
+        double li = lamv[i];
+        int rk = 0;
+        for (int q = 0; q < n; ++q) {
+            double lq = lamv[q];
+            rk += (lq > li || (lq == li && q < i)) ? 1 : 0;
+        }
+        if (rk < k) {
+            sel[rk] = i;
+            kept_part += li;
+        }
+    }
+    __syncthreads();
+    red[tid] = kept_part;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) { if (tid < o) red[tid] += red[tid + o]; __syncthreads(); }
+    double kept = red[0];
+    double sv = kept > 0.0 ? sqrt(kept) : 1.0;
+    double* lamout = lam_ptr(s, d.b, d.bond);
+    for (int r = tid; r < k; r += NT) {
+        double li = lamv[sel[r]];
+        lamout[r] = li > 0.0 ? sqrt(li) / sv : 0.0;
+    }
+    if (tid == 0) {
+        double wgt = total > 0.0 ? (total - kept) / total : 0.0;
+        w.kout[j] = k;
+        w.sout[j] = sv;
+        w.wout[j] = wgt > 0.0 ? wgt : 0.0;
+        if (!(kept == kept) || !(total == total)) atomicOr(w.flags, TN_FLAG_NAN);
+    }
+}
+
+// ------------------------------------------------------------------ eigenvectors
+// Replays the logged rotations in reverse order on the k selected unit vectors (each
+// thread owns whole columns, so no synchronization is needed during the replay), then
+// applies Q = H_0 ... H_{n-2} (reflectors in reverse order), writes V (n x k, FP64) for
+// the split and the new right tensor B_{bond+1} = V^+ (k x n) in storage precision.
+#define VECS_LDS_ELEMS 8192
+template <class T, bool LDS>
+__global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
+    __shared__ double2 zl[LDS ? VECS_LDS_ELEMS : 1];
+    __shared__ int lgi[NT];
+    __shared__ double2 lgcs[NT];
+    __shared__ double2 vbuf[512];
+    __shared__ double2 part[NT];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = d.n, tid = threadIdx.x;
+    const int k = w.kout[j];
+    const int* sel = w.sel + (size_t)j * w.nmax;
+    double2* Z = LDS ? zl : (w.zscratch + (size_t)j * w.nmax * s.chi);
+    for (int e = tid; e < n * k; e += NT) {
+        int r = e / k, c = e % k;
+        Z[e] = mk(r == sel[c] ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    // ---- replay rotations, newest first
+    const int nr = w.nrot[j];
+    const int* li = w.logi + (size_t)j * w.logcap;
+    const double2* lcs = w.logcs + (size_t)j * w.logcap;
+    for (int hi = nr; hi > 0; hi -= NT) {
+        int lo = hi - NT > 0 ? hi - NT : 0;
+        int cnt = hi - lo;
+        if (tid < cnt) {
+            lgi[tid] = li[lo + tid];
+            lgcs[tid] = lcs[lo + tid];
+        }
+        __syncthreads();
+        for (int c = tid; c < k; c += NT) {
+            for (int q = cnt - 1; q >= 0; --q) {
+                const int i = lgi[q];
+                const double cc = lgcs[q].x, ss = lgcs[q].y;
+                double x = Z[i * k + c].x, y = Z[(i + 1) * k + c].x;
+                Z[i * k + c].x = cc * x + ss * y;
+                Z[(i + 1) * k + c].x = -ss * x + cc * y;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- back-transformation by the Householder reflectors
+    const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    const double2* tau = w.tau + (size_t)j * w.nmax;
+    // thread layout: group g (4 groups) x column slot cl; columns c = cl, cl+64, ...
+    const int g = tid >> 6, cl = tid & 63;
+    for (int i = n - 2; i >= 0; --i) {
+        const int len = n - 1 - i;
+        const double2 t = tau[i];
+        if (t.x == 0.0 && t.y == 0.0) continue;  // uniform across the block
+        for (int r = tid; r < len; r += NT) vbuf[r] = refl[(size_t)i * w.nmax + r];
+        __syncthreads();
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            const int c = c0 + cl;
+            double2 acc = mk(0.0, 0.0);
+            if (c < k)
+                for (int r = g; r < len; r += 4) cfmac(acc, vbuf[r], Z[(i + 1 + r) * k + c]);
+            part[tid] = acc;
+            __syncthreads();
+            double2 wv = cadd(cadd(part[cl], part[64 + cl]), cadd(part[128 + cl], part[192 + cl]));
+            wv = cmul(t, wv);
+            if (c < k)
+                for (int r = g; r < len; r += 4) {
+                    double2 z = Z[(i + 1 + r) * k + c];
+                    double2 u = cmul(vbuf[r], wv);
+                    z.x -= u.x;
+                    z.y -= u.y;
+                    Z[(i + 1 + r) * k + c] = z;
+                }
+            __syncthreads();
+        }
+    }
+    // ---- outputs
+    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+    for (int e = tid; e < n * k; e += NT) {
+        int r = e / k, c = e % k;
+        double2 z = Z[e];
+        V[(size_t)r * s.chi + c] = z;
+    }
+    for (int e = tid; e < n * k; e += NT) {
+        int c = e / n, r = e % n;  // B_{bond+1}[c][r] = conj(V[r][c])
+        Br[e] = cconv<T>(cconj(Z[r * k + c]));
+    }
+}
+
+// ------------------------------------------------------------------ Hastings split
+template <class T>
+__global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n, double* glog, double* gwt) {
+    __shared__ T As[8 * 64], Bs[8 * 64];
+    ItemDims d;
+    const int j = blockIdx.y;
+    if (!item_dims(s, w, j, d)) return;
+    const int k = w.kout[j];
+    const double sv = w.sout[j];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.dims[(size_t)d.b * (s.L + 1) + d.bond + 1] = k;
+        int g = w.item0 + j;
+        glog[g] = log(sv);
+        gwt[g] = w.wout[j];
+    }
+    int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= d.m || tn * 64 >= k) return;
+    typedef typename real_of<T>::type R;
+    const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)j * w.theta_stride;
+    const double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    T* Bl = site_ptr<T>(s, d.b, d.bond);
+    const int n = d.n, chi = s.chi;
+    const R inv = (R)(1.0 / sv);
+    block_gemm<T, true, true, 8>(
+        d.m, k, n, tm * 64, tn * 64,
+        [&](int r, int q) { return th[(size_t)r * n + q]; },
+        [&](int q, int c) { return cconv<T>(V[(size_t)q * chi + c]); },
+        [&](int r, int c, T v) { Bl[(size_t)r * k + c] = cscale(v, inv); }, As, Bs);
+}
+
+// per instance: add the log-norms and discarded weights of its items (fixed order)
+__global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned char* mask,
+                               const double* glog, const double* gwt) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= s.B) return;
+    if (mask && mask[b]) return;
+    double lg = 0.0, wt = 0.0;
+    for (int t = 0; t < nb; ++t) {
+        lg += glog[(size_t)b * nb + t];
+        wt += gwt[(size_t)b * nb + t];
+    }
+    s.lognorm[b] += lg;
+    s.trunc[b] += wt;
+}
+
+// ------------------------------------------------------------------ host launchers
+#include "launch.h"
+
+template <class T>
+static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_t st, Prof* prof,
+                                 double* glog, double* gwt) {
+    const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
+    const int tkn = (s.chi + 63) / 64;
+    prof_begin(prof, TN_K_THETA, st);
+    hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+    prof_end(prof, TN_K_THETA, st);
+    prof_begin(prof, TN_K_GRAM, st);
+    hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    prof_end(prof, TN_K_GRAM, st);
+    prof_begin(prof, TN_K_HETRD, st);
+    if (w.nmax <= HETRD_LDS_N)
+        hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    else
+        hipLaunchKernelGGL(k_hetrd<false>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    prof_end(prof, TN_K_HETRD, st);
+    prof_begin(prof, TN_K_STEQR, st);
+    hipLaunchKernelGGL(k_steqr, dim3((w.nitems + 63) / 64), dim3(64), 0, st, s, w);
+    prof_end(prof, TN_K_STEQR, st);
+    prof_begin(prof, TN_K_VECS, st);
+    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    if ((size_t)w.nmax * s.chi <= VECS_LDS_ELEMS)
+        hipLaunchKernelGGL((k_vecs<T, true>), dim3(w.nitems), dim3(NT), 0, st, s, w);
+    else
+        hipLaunchKernelGGL((k_vecs<T, false>), dim3(w.nitems), dim3(NT), 0, st, s, w);
+    prof_end(prof, TN_K_VECS, st);
+    prof_begin(prof, TN_K_SPLIT, st);
+    hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+    prof_end(prof, TN_K_SPLIT, st);
+}
+
+void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream_t st, Prof* prof,
+                        double* glog, double* gwt) {
+    if (prec == 0)
+        launch_layer_chunk_t<double2>(s, w, st, prof, glog, gwt);
+    else
+        launch_layer_chunk_t<float2>(s, w, st, prof, glog, gwt);
+}
+
+void launch_reduce_items(const DevState& s, int nb, int parity, const unsigned char* mask, const double* glog,
+                         const double* gwt, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_items, dim3((s.B + 127) / 128), dim3(128), 0, st, s, nb, parity, mask, glog, gwt);
+}

@@ -1,0 +1,811 @@
+// C ABI of the batched TEBD-Lindblad library: state allocation inside a
+// caller-owned device arena, Trotter layer scheduling in chunks of independent
+// two-site updates, dissipative steps, measurement, state I/O and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "host_gates.h"
+#include "launch.h"
+
+#define TN_KIND_MPS 0
+#define TN_KIND_MPDO 1
+#define TN_KIND_PURIFIED 2
+
+typedef struct tn_model {
+    int L;
+    int d;
+    const double* h_bond;
+    int n_jumps;
+    const int* jump_site;
+    const double* jump_op;
+    const double* gamma;
+} tn_model;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(TN_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ profiling
+void prof_begin(Prof* p, int id, hipStream_t st) {
+    if (!p || !p->on) return;
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, st);
+    p->open[id] = e;
+}
+void prof_end(Prof* p, int id, hipStream_t st) {
+    if (!p || !p->on || !p->open[id]) return;
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, st);
+    p->ev[id].push_back(std::make_pair(p->open[id], e));
+    p->open[id] = nullptr;
+}
+
+// ------------------------------------------------------------------ state
+struct Layout {
+    size_t off_tens, off_lam, off_dims, off_lognorm, off_trunc, off_dsite, off_mask, off_jumped, off_glog, off_gwt,
+        off_gates, off_rnd, off_vals, off_nrm, off_jsite, off_jop, off_jLdL, off_gam, off_ceach, off_cmean, off_cvar,
+        off_flags, off_ws;
+    size_t ws_bytes, total;
+    // workspace sub-layout (update)
+    size_t u_theta, u_gram, u_refl, u_tau, u_dd, u_ee, u_logi, u_logcs, u_nrot, u_sel, u_kout, u_sout, u_wout, u_V,
+        u_z, u_p, u_bytes;
+    // workspace sub-layout (measurement)
+    size_t m_R, m_E, m_X, m_Y, m_W, m_bytes;
+};
+
+struct tn_state {
+    int kind, L, B, chi, chik, prec, dmax, njump;
+    int chunk, nbm, mmax, nmax, logcap, gstride, nbmax;
+    double cutoff;
+    std::vector<int> dsite;
+    TnModelHost model;
+    hipStream_t stream;
+    char* arena;
+    Layout lay;
+    size_t site_cap, esz;
+    // gate cache: tau -> slot
+    double slot_tau[2];
+    bool slot_valid[2];
+    Prof prof;
+};
+
+static inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int physical_dims(int kind, int L, int chik, const std::vector<int>& jsite, std::vector<int>& d) {
+    d.assign(L, 2);
+    if (kind == TN_KIND_MPDO) d.assign(L, 4);
+    if (kind == TN_KIND_PURIFIED)
+        for (int s : jsite) d[s] = 2 * chik;
+    return 0;
+}
+
+static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax, int prec, int chunk, int nbm,
+                           int njump, int logcap) {
+    const size_t esz = prec == 0 ? 16 : 8;
+    const size_t site_cap = (size_t)chi * dmax * chi;
+    const int mmax = chi * dmax, nmax = dmax * chi;
+    const int nbmax = (L - 1 + 1) / 2;
+    size_t o = 0;
+    ly.off_tens = o; o = al(o + (size_t)B * L * site_cap * esz);
+    ly.off_lam = o; o = al(o + (size_t)B * (L - 1) * chi * 8);
+    ly.off_dims = o; o = al(o + (size_t)B * (L + 1) * 4);
+    ly.off_lognorm = o; o = al(o + (size_t)B * 8);
+    ly.off_trunc = o; o = al(o + (size_t)B * 8);
+    ly.off_dsite = o; o = al(o + (size_t)L * 4);
+    ly.off_mask = o; o = al(o + (size_t)B);
+    ly.off_jumped = o; o = al(o + (size_t)B * 4);
+    ly.off_glog = o; o = al(o + (size_t)B * nbmax * 8);
+    ly.off_gwt = o; o = al(o + (size_t)B * nbmax * 8);
+    ly.off_gates = o; o = al(o + (size_t)2 * (L - 1) * 256 * 16);
+    ly.off_rnd = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 2 * 8);
+    ly.off_vals = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 8);
+    ly.off_nrm = o; o = al(o + (size_t)B * 8);
+    ly.off_jsite = o; o = al(o + 16 * 4);
+    ly.off_jop = o; o = al(o + 16 * 4 * 16);
+    ly.off_jLdL = o; o = al(o + 16 * 4 * 16);
+    ly.off_gam = o; o = al(o + 16 * 8);
+    ly.off_ceach = o; o = al(o + (size_t)B * L * L * 16);
+    ly.off_cmean = o; o = al(o + (size_t)L * L * 16);
+    ly.off_cvar = o; o = al(o + (size_t)L * L * 8);
+    ly.off_flags = o; o = al(o + 64);
+    ly.off_ws = o;
+    // update workspace
+    size_t u = 0;
+    ly.u_theta = u; u = al(u + (size_t)chunk * mmax * nmax * esz);
+    ly.u_gram = u; u = al(u + (size_t)chunk * nmax * nmax * 16);
+    ly.u_refl = u; u = al(u + (size_t)chunk * nmax * nmax * 16);
+    ly.u_tau = u; u = al(u + (size_t)chunk * nmax * 16);
+    ly.u_dd = u; u = al(u + (size_t)chunk * nmax * 8);
+    ly.u_ee = u; u = al(u + (size_t)chunk * nmax * 8);
+    ly.u_logi = u; u = al(u + (size_t)chunk * logcap * 4);
+    ly.u_logcs = u; u = al(u + (size_t)chunk * logcap * 16);
+    ly.u_nrot = u; u = al(u + (size_t)chunk * 4);
+    ly.u_sel = u; u = al(u + (size_t)chunk * nmax * 4);
+    ly.u_kout = u; u = al(u + (size_t)chunk * 4);
+    ly.u_sout = u; u = al(u + (size_t)chunk * 8);
+    ly.u_wout = u; u = al(u + (size_t)chunk * 8);
+    ly.u_V = u; u = al(u + (size_t)chunk * nmax * chi * 16);
+    ly.u_z = u; if ((size_t)nmax * chi > 8192) u = al(u + (size_t)chunk * nmax * chi * 16);
+    ly.u_p = u; if (nmax > 128) u = al(u + (size_t)chunk * ((size_t)nmax * (nmax + 1) / 2) * 16);
+    ly.u_bytes = u;
+    // measurement workspace
+    size_t m = 0;
+    size_t cc = (size_t)chi * chi;
+    ly.m_R = m; m = al(m + std::max((size_t)(L + 1) * nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
+    ly.m_E = m; m = al(m + std::max((size_t)nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
+    ly.m_X = m; m = al(m + (size_t)nbm * L * cc * esz);
+    ly.m_Y = m; m = al(m + (size_t)nbm * L * chi * dmax * chi * esz);
+    ly.m_W = m; m = al(m + (size_t)nbm * chi * dmax * chi * esz);
+    ly.m_bytes = m;
+    ly.ws_bytes = std::max(ly.u_bytes, ly.m_bytes);
+    ly.total = ly.off_ws + ly.ws_bytes;
+    (void)kind;
+}
+
+static int default_chunk(int L, int B, int chi, int dmax) {
+    const int nbmax = (L - 1 + 1) / 2;
+    long items = (long)B * nbmax;
+    int n = chi * dmax;
+    long cap = n <= 128 ? 8192 : (n <= 256 ? 1024 : 64);
+    return (int)std::max(1L, std::min(items, cap));
+}
+static int default_nbm(int B, int L, int chi) {
+    long per = (long)L * chi * chi;
+    long cap = std::max(1L, (long)(64L * 1024 * 1024 * 4) / std::max(1L, per));
+    return (int)std::max(1L, std::min((long)B, std::min(cap, 256L)));
+}
+static int log_capacity(int nmax) { return std::max(64, 4 * nmax * nmax); }
+
+static bool model_ok(const tn_model* m, std::string& why) {
+    if (!m) { why = "model is null"; return false; }
+    if (m->L < 2) { why = "L must be >= 2"; return false; }
+    if (m->d != 2) { why = "local dimension d must be 2"; return false; }
+    if (!m->h_bond) { why = "h_bond is null"; return false; }
+    if (m->n_jumps < 0 || m->n_jumps > 8) { why = "n_jumps must be in 0..8"; return false; }
+    if (m->n_jumps > 0 && (!m->jump_site || !m->jump_op || !m->gamma)) { why = "jump arrays are null"; return false; }
+    for (int q = 0; q < m->n_jumps; ++q) {
+        if (m->jump_site[q] < 0 || m->jump_site[q] >= m->L) { why = "jump site out of range"; return false; }
+        if (!(m->gamma[q] >= 0)) { why = "negative rate"; return false; }
+    }
+    return true;
+}
+
+extern "C" size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int chi_k_max, int precision,
+                                  int chunk_items) {
+    if (L < 2 || batch < 1 || chi_max < 1 || (precision != 0 && precision != 1)) return 0;
+    if (kind < 0 || kind > 2) return 0;
+    int dmax = kind == TN_KIND_MPDO ? 4 : (kind == TN_KIND_PURIFIED ? 2 * std::max(1, chi_k_max) : 2);
+    int chunk = chunk_items > 0 ? chunk_items : default_chunk(L, batch, chi_max, dmax);
+    int nbm = default_nbm(batch, L, chi_max);
+    Layout ly;
+    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, 8, log_capacity(dmax * chi_max));
+    return ly.total;
+}
+
+template <class T>
+static inline T* at(tn_state* s, size_t off) { return reinterpret_cast<T*>(s->arena + off); }
+
+static DevState dev_state(tn_state* s) {
+    DevState d;
+    d.kind = s->kind;
+    d.L = s->L;
+    d.B = s->B;
+    d.chi = s->chi;
+    d.dmax = s->dmax;
+    d.site_cap = s->site_cap;
+    d.tens = s->arena + s->lay.off_tens;
+    d.lam = at<double>(s, s->lay.off_lam);
+    d.dims = at<int>(s, s->lay.off_dims);
+    d.lognorm = at<double>(s, s->lay.off_lognorm);
+    d.trunc = at<double>(s, s->lay.off_trunc);
+    d.dsite = at<int>(s, s->lay.off_dsite);
+    d.cutoff2 = s->cutoff * s->cutoff;
+    return d;
+}
+
+// packed host layout of one instance
+static size_t packed_tensor_elems(const tn_state* s, const int* dims) {
+    size_t n = 0;
+    for (int i = 0; i < s->L; ++i) n += (size_t)dims[i] * s->dsite[i] * dims[i + 1];
+    return n;
+}
+
+extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double* tensors, const double* lambdas,
+                                double lognorm);
+extern "C" int mps_replicate(void* h, int src);
+
+extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch, int chi_max, int chi_k_max,
+                         int precision, const int* init_occ, double sv_cutoff, void* arena, size_t arena_bytes,
+                         void* hip_stream) {
+    g_err.clear();
+    if (!out) return fail(TN_EINVAL, "out is null");
+    *out = nullptr;
+    std::string why;
+    if (!model_ok(model, why)) return fail(TN_EINVAL, why);
+    if (kind < 0 || kind > 2) return fail(TN_EINVAL, "unknown kind");
+    if (batch < 1 || chi_max < 1) return fail(TN_EINVAL, "batch and chi_max must be >= 1");
+    if (chi_max > 256) return fail(TN_EINVAL, "chi_max must be <= 256");
+    if (precision != 0 && precision != 1) return fail(TN_EINVAL, "precision must be TN_FP64 or TN_SPLIT");
+    if (!init_occ) return fail(TN_EINVAL, "init_occ is null");
+    if (!arena) return fail(TN_EINVAL, "arena is null");
+    if (!(sv_cutoff >= 0.0 && sv_cutoff < 1.0)) return fail(TN_EINVAL, "sv_cutoff must be in [0, 1)");
+    if (kind == TN_KIND_PURIFIED && (chi_k_max < 1 || chi_k_max > 4))
+        return fail(TN_EINVAL, "chi_k_max must be in 1..4");
+    const int L = model->L;
+    for (int i = 0; i < L; ++i)
+        if (init_occ[i] != 0 && init_occ[i] != 1) return fail(TN_EINVAL, "init_occ entries must be 0 or 1");
+    tn_state* s = new tn_state();
+    s->kind = kind;
+    s->L = L;
+    s->B = batch;
+    s->chi = chi_max;
+    s->chik = kind == TN_KIND_PURIFIED ? chi_k_max : 1;
+    s->prec = precision;
+    s->cutoff = sv_cutoff;
+    s->njump = model->n_jumps;
+    s->model.L = L;
+    s->model.h_bond.assign(model->h_bond, model->h_bond + (size_t)(L - 1) * 32);
+    for (int q = 0; q < model->n_jumps; ++q) {
+        s->model.jump_site.push_back(model->jump_site[q]);
+        s->model.gamma.push_back(model->gamma[q]);
+        for (int e = 0; e < 8; ++e) s->model.jump_op.push_back(model->jump_op[8 * q + e]);
+    }
+    physical_dims(kind, L, s->chik, s->model.jump_site, s->dsite);
+    s->dmax = *std::max_element(s->dsite.begin(), s->dsite.end());
+    for (int b = 0; b + 1 < L; ++b)
+        if (s->dsite[b] * s->dsite[b + 1] > 16) {
+            delete s;
+            return fail(TN_EINVAL, "bond physical dimension d_b*d_{b+1} exceeds 16 (adjacent purified jump sites)");
+        }
+    if (chi_max * s->dmax > 512) {
+        delete s;
+        return fail(TN_EINVAL, "chi_max * local dimension must be <= 512");
+    }
+    s->site_cap = (size_t)chi_max * s->dmax * chi_max;
+    s->esz = precision == 0 ? 16 : 8;
+    s->mmax = chi_max * s->dmax;
+    s->nmax = s->dmax * chi_max;
+    s->chunk = default_chunk(L, batch, chi_max, s->dmax);
+    s->nbm = default_nbm(batch, L, chi_max);
+    s->logcap = log_capacity(s->nmax);
+    s->gstride = 256;
+    s->nbmax = (L - 1 + 1) / 2;
+    compute_layout(s->lay, kind, L, batch, chi_max, s->dmax, precision, s->chunk, s->nbm, 8, s->logcap);
+    if (arena_bytes < s->lay.total) {
+        size_t need = s->lay.total;
+        delete s;
+        char buf[128];
+        snprintf(buf, sizeof buf, "arena too small: need %zu bytes", need);
+        return fail(TN_ENOMEM, buf);
+    }
+    s->arena = reinterpret_cast<char*>(arena);
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->slot_valid[0] = s->slot_valid[1] = false;
+    // constant tables
+    int rc;
+    {
+        hipError_t e = hipMemcpyAsync(s->arena + s->lay.off_dsite, s->dsite.data(), L * sizeof(int),
+                                      hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) { delete s; return fail(TN_EHIP, hipGetErrorString(e)); }
+        std::vector<int> js(s->model.jump_site);
+        std::vector<double2> jo, jl;
+        for (int q = 0; q < s->njump; ++q) {
+            double2 o[4];
+            for (int e2 = 0; e2 < 4; ++e2) o[e2] = mk(s->model.jump_op[8 * q + 2 * e2], s->model.jump_op[8 * q + 2 * e2 + 1]);
+            for (int e2 = 0; e2 < 4; ++e2) jo.push_back(o[e2]);
+            // L^+ L
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                    double2 acc = mk(0, 0);
+                    for (int k = 0; k < 2; ++k) cfmac(acc, o[k * 2 + r], o[k * 2 + c]);
+                    jl.push_back(acc);
+                }
+        }
+        if (s->njump) {
+            hipMemcpyAsync(s->arena + s->lay.off_jsite, js.data(), js.size() * 4, hipMemcpyHostToDevice, s->stream);
+            hipMemcpyAsync(s->arena + s->lay.off_jop, jo.data(), jo.size() * 16, hipMemcpyHostToDevice, s->stream);
+            hipMemcpyAsync(s->arena + s->lay.off_jLdL, jl.data(), jl.size() * 16, hipMemcpyHostToDevice, s->stream);
+            hipMemcpyAsync(s->arena + s->lay.off_gam, s->model.gamma.data(), s->njump * 8, hipMemcpyHostToDevice,
+                           s->stream);
+        }
+        hipMemsetAsync(s->arena + s->lay.off_flags, 0, 64, s->stream);
+        hipMemsetAsync(s->arena + s->lay.off_mask, 0, (size_t)batch, s->stream);
+    }
+    // product state, instance 0, then replicate
+    std::vector<int> dims(L + 1, 1);
+    std::vector<double> tens;
+    for (int i = 0; i < L; ++i) {
+        int d = s->dsite[i];
+        std::vector<double> t(2 * d, 0.0);
+        int p;
+        if (kind == TN_KIND_MPS) p = init_occ[i];
+        else if (kind == TN_KIND_MPDO) p = 3 * init_occ[i];
+        else p = init_occ[i] * (d / 2);
+        t[2 * p] = 1.0;
+        tens.insert(tens.end(), t.begin(), t.end());
+    }
+    std::vector<double> lams(L - 1, 1.0);
+    rc = mps_set_instance(s, 0, dims.data(), tens.data(), lams.data(), 0.0);
+    if (rc) { delete s; return rc; }
+    rc = mps_replicate(s, 0);
+    if (rc) { delete s; return rc; }
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) { delete s; return fail(TN_EHIP, hipGetErrorString(e)); }
+    *out = s;
+    return TN_OK;
+}
+
+extern "C" int mps_free(void* h) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    hipStreamSynchronize(s->stream);
+    for (int k = 0; k < TN_K_COUNT; ++k)
+        for (auto& pr : s->prof.ev[k]) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    delete s;
+    return TN_OK;
+}
+
+extern "C" const char* mps_last_error(void) { return g_err.c_str(); }
+
+extern "C" size_t mps_instance_tensor_capacity(const void* h) {
+    const tn_state* s = reinterpret_cast<const tn_state*>(h);
+    return s ? (size_t)s->L * s->site_cap : 0;
+}
+extern "C" size_t mps_instance_lambda_capacity(const void* h) {
+    const tn_state* s = reinterpret_cast<const tn_state*>(h);
+    return s ? (size_t)(s->L - 1) * s->chi : 0;
+}
+
+extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double* tensors, const double* lambdas,
+                                double lognorm) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s || !dims || !tensors || !lambdas) return fail(TN_EINVAL, "null argument");
+    if (inst < 0 || inst >= s->B) return fail(TN_EINVAL, "instance out of range");
+    if (dims[0] != 1 || dims[s->L] != 1) return fail(TN_EINVAL, "dims[0] and dims[L] must be 1");
+    for (int i = 1; i < s->L; ++i)
+        if (dims[i] < 1 || dims[i] > s->chi) return fail(TN_EINVAL, "bond dimension out of range");
+    size_t off = 0;
+    for (int i = 0; i < s->L; ++i) {
+        size_t ne = (size_t)dims[i] * s->dsite[i] * dims[i + 1];
+        char* dst = s->arena + s->lay.off_tens + (((size_t)inst * s->L + i) * s->site_cap) * s->esz;
+        if (s->prec == 0) {
+            HIPCHK(hipMemcpyAsync(dst, tensors + 2 * off, ne * 16, hipMemcpyHostToDevice, s->stream));
+        } else {
+            std::vector<float> f(2 * ne);
+            for (size_t e = 0; e < 2 * ne; ++e) f[e] = (float)tensors[2 * off + e];
+            HIPCHK(hipMemcpyAsync(dst, f.data(), ne * 8, hipMemcpyHostToDevice, s->stream));
+            HIPCHK(hipStreamSynchronize(s->stream));
+        }
+        off += ne;
+    }
+    std::vector<double> lam((size_t)(s->L - 1) * s->chi, 0.0);
+    size_t lo = 0;
+    for (int b = 0; b + 1 < s->L; ++b) {
+        for (int a = 0; a < dims[b + 1]; ++a) lam[(size_t)b * s->chi + a] = lambdas[lo + a];
+        lo += dims[b + 1];
+    }
+    HIPCHK(hipMemcpyAsync(at<double>(s, s->lay.off_lam) + (size_t)inst * (s->L - 1) * s->chi, lam.data(),
+                          lam.size() * 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(at<int>(s, s->lay.off_dims) + (size_t)inst * (s->L + 1), dims, (s->L + 1) * 4,
+                          hipMemcpyHostToDevice, s->stream));
+    double z = 0.0;
+    HIPCHK(hipMemcpyAsync(at<double>(s, s->lay.off_lognorm) + inst, &lognorm, 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(at<double>(s, s->lay.off_trunc) + inst, &z, 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+extern "C" int mps_get_instance(const void* h, int inst, int* dims, double* tensors, double* lambdas,
+                                double* lognorm, double* trunc) {
+    const tn_state* s = reinterpret_cast<const tn_state*>(h);
+    if (!s || !dims) return fail(TN_EINVAL, "null argument");
+    if (inst < 0 || inst >= s->B) return fail(TN_EINVAL, "instance out of range");
+    tn_state* sm = const_cast<tn_state*>(s);
+    HIPCHK(hipMemcpyAsync(dims, at<int>(sm, s->lay.off_dims) + (size_t)inst * (s->L + 1), (s->L + 1) * 4,
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (tensors) {
+        size_t off = 0;
+        for (int i = 0; i < s->L; ++i) {
+            size_t ne = (size_t)dims[i] * s->dsite[i] * dims[i + 1];
+            const char* src = s->arena + s->lay.off_tens + (((size_t)inst * s->L + i) * s->site_cap) * s->esz;
+            if (s->prec == 0) {
+                HIPCHK(hipMemcpyAsync(tensors + 2 * off, src, ne * 16, hipMemcpyDeviceToHost, s->stream));
+            } else {
+                std::vector<float> f(2 * ne);
+                HIPCHK(hipMemcpyAsync(f.data(), src, ne * 8, hipMemcpyDeviceToHost, s->stream));
+                HIPCHK(hipStreamSynchronize(s->stream));
+                for (size_t e = 0; e < 2 * ne; ++e) tensors[2 * off + e] = f[e];
+            }
+            off += ne;
+        }
+    }
+    if (lambdas) {
+        std::vector<double> lam((size_t)(s->L - 1) * s->chi);
+        HIPCHK(hipMemcpyAsync(lam.data(), at<double>(sm, s->lay.off_lam) + (size_t)inst * (s->L - 1) * s->chi,
+                              lam.size() * 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        size_t lo = 0;
+        for (int b = 0; b + 1 < s->L; ++b) {
+            for (int a = 0; a < dims[b + 1]; ++a) lambdas[lo + a] = lam[(size_t)b * s->chi + a];
+            lo += dims[b + 1];
+        }
+    }
+    if (lognorm)
+        HIPCHK(hipMemcpyAsync(lognorm, at<double>(sm, s->lay.off_lognorm) + inst, 8, hipMemcpyDeviceToHost, s->stream));
+    if (trunc)
+        HIPCHK(hipMemcpyAsync(trunc, at<double>(sm, s->lay.off_trunc) + inst, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+extern "C" int mps_replicate(void* h, int src) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (src < 0 || src >= s->B) return fail(TN_EINVAL, "instance out of range");
+    const size_t tb = (size_t)s->L * s->site_cap * s->esz;
+    const size_t lb = (size_t)(s->L - 1) * s->chi * 8;
+    const size_t db = (size_t)(s->L + 1) * 4;
+    for (int b = 0; b < s->B; ++b) {
+        if (b == src) continue;
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_tens + (size_t)b * tb, s->arena + s->lay.off_tens + (size_t)src * tb,
+                              tb, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_lam + (size_t)b * lb, s->arena + s->lay.off_lam + (size_t)src * lb,
+                              lb, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_dims + (size_t)b * db, s->arena + s->lay.off_dims + (size_t)src * db,
+                              db, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_lognorm + (size_t)b * 8, s->arena + s->lay.off_lognorm + (size_t)src * 8,
+                              8, hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_trunc + (size_t)b * 8, s->arena + s->lay.off_trunc + (size_t)src * 8,
+                              8, hipMemcpyDeviceToDevice, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ gates
+static int upload_gates(tn_state* s, int slot, double tau) {
+    if (s->slot_valid[slot] && s->slot_tau[slot] == tau) return TN_OK;
+    std::vector<double> all((size_t)(s->L - 1) * s->gstride * 2, 0.0);
+    for (int b = 0; b + 1 < s->L; ++b) {
+        std::vector<double> g;
+        try {
+            g = build_bond_gate(s->kind == TN_KIND_MPDO ? 1 : 0, s->model, b, tau);
+        } catch (const std::exception& ex) {
+            return fail(TN_ENUMERIC, ex.what());
+        }
+        if (s->kind == TN_KIND_PURIFIED) g = embed_purified(g, s->dsite[b] / 2, s->dsite[b + 1] / 2);
+        std::copy(g.begin(), g.end(), all.begin() + (size_t)b * s->gstride * 2);
+    }
+    HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16, all.data(),
+                          all.size() * 8, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->slot_tau[slot] = tau;
+    s->slot_valid[slot] = true;
+    return TN_OK;
+}
+
+extern "C" int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out) {
+    std::string why;
+    if (!model_ok(model, why)) return fail(TN_EINVAL, why);
+    if (!out || bond < 0 || bond > model->L - 2) return fail(TN_EINVAL, "bad bond or null output");
+    TnModelHost m;
+    m.L = model->L;
+    m.h_bond.assign(model->h_bond, model->h_bond + (size_t)(model->L - 1) * 32);
+    for (int q = 0; q < model->n_jumps; ++q) {
+        m.jump_site.push_back(model->jump_site[q]);
+        m.gamma.push_back(model->gamma[q]);
+        for (int e = 0; e < 8; ++e) m.jump_op.push_back(model->jump_op[8 * q + e]);
+    }
+    try {
+        std::vector<double> g = build_bond_gate(kind == TN_KIND_MPDO ? 1 : 0, m, bond, tau);
+        std::copy(g.begin(), g.end(), out);
+    } catch (const std::exception& ex) {
+        return fail(TN_ENUMERIC, ex.what());
+    }
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ flags
+static int check_flags(tn_state* s) {
+    int flags = 0;
+    HIPCHK(hipMemcpyAsync(&flags, s->arena + s->lay.off_flags, 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (flags) {
+        HIPCHK(hipMemsetAsync(s->arena + s->lay.off_flags, 0, 4, s->stream));
+        if (flags & TN_FLAG_NAN) return fail(TN_ENUMERIC, "NaN in a two-site update");
+        if (flags & TN_FLAG_LOGFULL) return fail(TN_ENOCONV, "rotation log capacity exceeded");
+        if (flags & TN_FLAG_NOCONV) return fail(TN_ENOCONV, "tridiagonal QL did not converge");
+    }
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ TEBD
+static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mask_dev) {
+    const int nb = parity <= s->L - 2 ? ((s->L - 2 - parity) / 2 + 1) : 0;
+    if (nb == 0) return TN_OK;
+    DevState ds = dev_state(s);
+    const long total = (long)s->B * nb;
+    char* ws = s->arena + s->lay.off_ws;
+    double* glog = at<double>(s, s->lay.off_glog);
+    double* gwt = at<double>(s, s->lay.off_gwt);
+    for (long i0 = 0; i0 < total; i0 += s->chunk) {
+        DevWork w;
+        w.item0 = (int)i0;
+        w.nitems = (int)std::min((long)s->chunk, total - i0);
+        w.parity = parity;
+        w.nb = nb;
+        w.mask = mask_dev;
+        w.gates = reinterpret_cast<const double2*>(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16);
+        w.gstride = s->gstride;
+        w.mmax = s->mmax;
+        w.nmax = s->nmax;
+        w.theta_stride = (size_t)s->mmax * s->nmax;
+        w.theta = ws + s->lay.u_theta;
+        w.gram = reinterpret_cast<double2*>(ws + s->lay.u_gram);
+        w.refl = reinterpret_cast<double2*>(ws + s->lay.u_refl);
+        w.tau = reinterpret_cast<double2*>(ws + s->lay.u_tau);
+        w.dd = reinterpret_cast<double*>(ws + s->lay.u_dd);
+        w.ee = reinterpret_cast<double*>(ws + s->lay.u_ee);
+        w.logcap = s->logcap;
+        w.logi = reinterpret_cast<int*>(ws + s->lay.u_logi);
+        w.logcs = reinterpret_cast<double2*>(ws + s->lay.u_logcs);
+        w.nrot = reinterpret_cast<int*>(ws + s->lay.u_nrot);
+        w.sel = reinterpret_cast<int*>(ws + s->lay.u_sel);
+        w.kout = reinterpret_cast<int*>(ws + s->lay.u_kout);
+        w.sout = reinterpret_cast<double*>(ws + s->lay.u_sout);
+        w.wout = reinterpret_cast<double*>(ws + s->lay.u_wout);
+        w.V = reinterpret_cast<double2*>(ws + s->lay.u_V);
+        w.zscratch = reinterpret_cast<double2*>(ws + s->lay.u_z);
+        w.pscratch = reinterpret_cast<double2*>(ws + s->lay.u_p);
+        w.flags = at<int>(s, s->lay.off_flags);
+        launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
+        HIPCHK(hipGetLastError());
+    }
+    launch_reduce_items(ds, nb, parity, mask_dev, glog, gwt, s->stream);
+    HIPCHK(hipGetLastError());
+    return TN_OK;
+}
+
+extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsigned char* mask,
+                         double* trunc_weight_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (order != 1 && order != 2) return fail(TN_EINVAL, "order must be 1 or 2");
+    if (n_steps < 0) return fail(TN_EINVAL, "n_steps must be >= 0");
+    if (!(std::isfinite(dt))) return fail(TN_EINVAL, "dt must be finite");
+    int rc;
+    // layer sequence (parity, slot); slot 0 = dt (order 1) or dt/2 (order 2), slot 1 = dt (order 2)
+    std::vector<std::pair<int, int>> layers;
+    if (order == 1) {
+        if ((rc = upload_gates(s, 0, dt))) return rc;
+        layers = {{0, 0}, {1, 0}};
+    } else {
+        if ((rc = upload_gates(s, 0, dt / 2))) return rc;
+        if ((rc = upload_gates(s, 1, dt))) return rc;
+        layers = {{1, 0}, {0, 1}, {1, 0}};
+    }
+    const unsigned char* mdev = nullptr;
+    if (mask) {
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_mask, mask, s->B, hipMemcpyHostToDevice, s->stream));
+        mdev = reinterpret_cast<const unsigned char*>(s->arena + s->lay.off_mask);
+    }
+    for (int st = 0; st < n_steps; ++st)
+        for (auto& ly : layers)
+            if ((rc = run_layer(s, ly.first, ly.second, mdev))) return rc;
+    if ((rc = check_flags(s))) {
+        if (trunc_weight_out)
+            hipMemcpy(trunc_weight_out, s->arena + s->lay.off_trunc, (size_t)s->B * 8, hipMemcpyDeviceToHost);
+        return rc;
+    }
+    if (trunc_weight_out) {
+        HIPCHK(hipMemcpyAsync(trunc_weight_out, s->arena + s->lay.off_trunc, (size_t)s->B * 8, hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ measurement
+static MeasWork meas_work(tn_state* s, int b0, int nbm) {
+    char* ws = s->arena + s->lay.off_ws;
+    MeasWork mw;
+    mw.b0 = b0;
+    mw.nbm = nbm;
+    mw.R = ws + s->lay.m_R;
+    mw.E = ws + s->lay.m_E;
+    mw.X = ws + s->lay.m_X;
+    mw.Y = ws + s->lay.m_Y;
+    mw.W = ws + s->lay.m_W;
+    mw.C = at<double2>(s, s->lay.off_ceach) + (size_t)b0 * s->L * s->L;
+    mw.nrm = at<double>(s, s->lay.off_nrm) + b0;
+    return mw;
+}
+
+// per instance: normalization or the lognorm scale; norm_out
+__global__ void k_meas_scale(DevState s, double2* Ceach, double* nrm, int mode) {
+    const int b = blockIdx.x;
+    const int L = s.L;
+    double f;
+    double n = nrm[b];
+    if (mode == 0) f = 1.0 / n;                          // normalized
+    else if (mode == 1) f = exp(2.0 * s.lognorm[b]);      // linear (unnormalized)
+    else f = 1.0 / n;                                     // MPDO: divide by trace
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x) Ceach[(size_t)b * L * L + e] = cscale(Ceach[(size_t)b * L * L + e], f);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (mode == 2) nrm[b] = n * exp(s.lognorm[b]);
+        else nrm[b] = n * exp(2.0 * s.lognorm[b]);
+    }
+}
+// batch mean and variance per entry (fixed summation order)
+__global__ void k_meas_stats(int B, int LL, const double2* Ceach, double2* mean, double* var) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= LL) return;
+    double2 m = mk(0, 0);
+    for (int b = 0; b < B; ++b) m = cadd(m, Ceach[(size_t)b * LL + e]);
+    m = cscale(m, 1.0 / B);
+    double v = 0.0;
+    for (int b = 0; b < B; ++b) {
+        double2 d = csub(Ceach[(size_t)b * LL + e], m);
+        v += d.x * d.x + d.y * d.y;
+    }
+    mean[e] = m;
+    var[e] = B > 1 ? v / (B - 1) : 0.0;
+}
+
+extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_var, double* C_each, double* norm_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!C_mean) return fail(TN_EINVAL, "C_mean is null");
+    DevState ds = dev_state(s);
+    prof_begin(&s->prof, TN_K_MEASURE, s->stream);
+    for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
+        int nbm = std::min(s->nbm, s->B - b0);
+        MeasWork mw = meas_work(s, b0, nbm);
+        if (s->kind == TN_KIND_MPDO) launch_measure_mpdo(s->prec, ds, mw, s->stream);
+        else launch_measure_mps(s->prec, ds, mw, s->stream);
+        HIPCHK(hipGetLastError());
+    }
+    int mode = s->kind == TN_KIND_MPDO ? 2 : ((s->kind == TN_KIND_MPS && !normalize) ? 1 : 0);
+    double2* ce = at<double2>(s, s->lay.off_ceach);
+    double* nr = at<double>(s, s->lay.off_nrm);
+    hipLaunchKernelGGL(k_meas_scale, dim3(s->B), dim3(256), 0, s->stream, ds, ce, nr, mode);
+    const int LL = s->L * s->L;
+    hipLaunchKernelGGL(k_meas_stats, dim3((LL + 255) / 256), dim3(256), 0, s->stream, s->B, LL, ce,
+                       at<double2>(s, s->lay.off_cmean), at<double>(s, s->lay.off_cvar));
+    HIPCHK(hipGetLastError());
+    prof_end(&s->prof, TN_K_MEASURE, s->stream);
+    HIPCHK(hipMemcpyAsync(C_mean, s->arena + s->lay.off_cmean, (size_t)LL * 16, hipMemcpyDeviceToHost, s->stream));
+    if (C_var)
+        HIPCHK(hipMemcpyAsync(C_var, s->arena + s->lay.off_cvar, (size_t)LL * 8, hipMemcpyDeviceToHost, s->stream));
+    if (C_each)
+        HIPCHK(hipMemcpyAsync(C_each, ce, (size_t)s->B * LL * 16, hipMemcpyDeviceToHost, s->stream));
+    if (norm_out) HIPCHK(hipMemcpyAsync(norm_out, nr, (size_t)s->B * 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ dissipative step
+extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int noise_kind, int* jumped_out,
+                           unsigned char* mask_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (s->njump == 0) return fail(TN_EINVAL, "model has no jump operators");
+    DevState ds = dev_state(s);
+    const int* jsite = at<int>(s, s->lay.off_jsite);
+    const double2* jop = at<double2>(s, s->lay.off_jop);
+    const double* gam = at<double>(s, s->lay.off_gam);
+    prof_begin(&s->prof, TN_K_JUMPS, s->stream);
+    if (mode == 0) {
+        if (s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QT jumps need kind MPS");
+        if (!rnd) return fail(TN_EINVAL, "rnd is null");
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, (size_t)s->B * 8, hipMemcpyHostToDevice, s->stream));
+        std::vector<double2> jl(4 * s->njump);
+        // L^+L on the host (the device copy is used by no kernel argument list here)
+        for (int q = 0; q < s->njump; ++q) {
+            double2 o[4];
+            for (int e = 0; e < 4; ++e) o[e] = mk(s->model.jump_op[8 * q + 2 * e], s->model.jump_op[8 * q + 2 * e + 1]);
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) {
+                    double2 acc = mk(0, 0);
+                    for (int k = 0; k < 2; ++k) cfmac(acc, o[k * 2 + r], o[k * 2 + c]);
+                    jl[4 * q + r * 2 + c] = acc;
+                }
+        }
+        for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
+            int nbm = std::min(s->nbm, s->B - b0);
+            MeasWork mw = meas_work(s, b0, nbm);
+            double* vals = at<double>(s, s->lay.off_vals);
+            launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals, s->stream);
+            launch_qt_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam, vals, mw.nrm,
+                            at<double>(s, s->lay.off_rnd), at<int>(s, s->lay.off_jumped),
+                            reinterpret_cast<unsigned char*>(s->arena + s->lay.off_mask), s->stream);
+            HIPCHK(hipGetLastError());
+        }
+        if (jumped_out)
+            HIPCHK(hipMemcpyAsync(jumped_out, s->arena + s->lay.off_jumped, (size_t)s->B * 4, hipMemcpyDeviceToHost,
+                                  s->stream));
+        if (mask_out)
+            HIPCHK(hipMemcpyAsync(mask_out, s->arena + s->lay.off_mask, (size_t)s->B, hipMemcpyDeviceToHost, s->stream));
+    } else if (mode == 1) {
+        if (s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QSD noise needs kind MPS");
+        if (!rnd) return fail(TN_EINVAL, "rnd is null");
+        if (noise_kind != 0 && noise_kind != 1) return fail(TN_EINVAL, "unknown noise kind");
+        size_t n = (size_t)s->B * s->njump * (noise_kind == 0 ? 2 : 1);
+        HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, n * 8, hipMemcpyHostToDevice, s->stream));
+        launch_qsd_apply(s->prec, ds, dt, s->njump, jsite, jop, gam, at<double>(s, s->lay.off_rnd), noise_kind,
+                         s->stream);
+        HIPCHK(hipGetLastError());
+    } else if (mode == 2) {
+        if (s->kind != TN_KIND_PURIFIED) return fail(TN_EINVAL, "Kraus compression needs kind PURIFIED");
+        std::vector<double2> hop(4 * s->njump);
+        for (int q = 0; q < 4 * s->njump; ++q) hop[q] = mk(s->model.jump_op[2 * q], s->model.jump_op[2 * q + 1]);
+        launch_kraus(s->prec, ds, dt, s->njump, s->model.jump_site.data(), hop.data(), s->model.gamma.data(), s->chik,
+                     s->stream);
+        HIPCHK(hipGetLastError());
+    } else {
+        return fail(TN_EINVAL, "unknown mode");
+    }
+    prof_end(&s->prof, TN_K_JUMPS, s->stream);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ timing
+extern "C" int tn_prof_enable(void* h, int on) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    hipStreamSynchronize(s->stream);
+    for (int k = 0; k < TN_K_COUNT; ++k) {
+        for (auto& pr : s->prof.ev[k]) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+        s->prof.ev[k].clear();
+        s->prof.open[k] = nullptr;
+    }
+    s->prof.on = on != 0;
+    return TN_OK;
+}
+
+extern "C" int tn_prof_query(void* h, int kernel_id, double* total_ms, long long* launches) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (kernel_id < 0 || kernel_id >= TN_K_COUNT) return fail(TN_EINVAL, "bad kernel id");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    double tot = 0.0;
+    for (auto& pr : s->prof.ev[kernel_id]) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (long long)s->prof.ev[kernel_id].size();
+    return TN_OK;
+}

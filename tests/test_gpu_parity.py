@@ -1,0 +1,182 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+FP64 mode: <= 1e-10 on gauge-invariant results (correlations, norms, traces, jump choices)
+with chi not binding.  SPLIT mode (complex64 MFMA contractions, FP64 SVD): <= 1e-5
+normwise relative on the correlation matrix (max|dC| / max|C|).
+"""
+import numpy as np
+import pytest
+
+import tn_inputs
+from oracle import model as M, tebd, measure, stochastic, kraus, exact
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2609_18841_amd import api  # noqa: E402
+
+
+def _oracle_gate_fn(mdl, kind, dks=None):
+    cache = {}
+
+    def fn(b, tau):
+        key = (b, tau)
+        if key not in cache:
+            if kind == "mpdo":
+                cache[key] = M.gate_liouville(mdl, b, tau)
+            elif kind == "purified":
+                cache[key] = M.purified_gate(M.gate_heff(mdl, b, tau), dks[b], dks[b + 1])
+            else:
+                cache[key] = M.gate_heff(mdl, b, tau)
+        return cache[key]
+    return fn
+
+
+def _normwise(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_mps_heff_trotter_matches_oracle(prec, tol):
+    L, chi, dt, nsteps = 8, 16, 0.1, 5
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    st = tebd.product_state(occ, "mps")
+    fn = _oracle_gate_fn(mdl, "mps")
+    for _ in range(nsteps):
+        tebd.trotter_step(st, fn, 1, dt, chi, 1e-12)
+    C_o, n_o = measure.corr_mps(st, normalize=True)
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 2, chi, occ, precision=prec,
+                  sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    for _ in range(nsteps):
+        g.tebd_step(dt, order=1)
+    C_g, var, _, nrm = g.measure_corr(normalize=1)
+    assert _normwise(C_g, C_o) < tol
+    assert abs(nrm[0] - n_o) / n_o < tol
+    g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_mpdo_second_order_matches_oracle(prec, tol):
+    L, chi, dt, nsteps = 6, 64, 0.05, 6
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    st = tebd.product_state(occ, "mpdo")
+    fn = _oracle_gate_fn(mdl, "mpdo")
+    for _ in range(nsteps):
+        tebd.trotter_step(st, fn, 2, dt, chi, 1e-12)
+    C_o, tr_o = measure.corr_mpdo(st)
+    g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 1, chi, occ, precision=prec,
+                  sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    g.tebd_step(dt, order=2, n_steps=nsteps)
+    C_g, _, _, tr = g.measure_corr()
+    assert _normwise(C_g, C_o) < tol
+    assert abs(tr[0] - tr_o.real) < tol
+    # the exact Trotter product keeps Tr rho = 1 (Liouvillian gates are trace preserving)
+    assert abs(tr[0] - 1.0) < 10 * tol
+    g.close()
+
+
+def test_qsd_batch_matches_oracle_per_trajectory():
+    L, chi, dt, nsteps, B = 6, 8, 0.02, 10, 4
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    noise = tn_inputs.normals(123, (nsteps, B, 2, 2))
+    fn = _oracle_gate_fn(mdl, "mps")
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ)
+    for k in range(nsteps):
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_QSD, dt, noise[k].reshape(-1), api.NOISE_GAUSS)
+    _, _, C_each, nrm = g.measure_corr(normalize=0, each=True)
+    for b in range(B):
+        st = tebd.product_state(occ, "mps")
+        for k in range(nsteps):
+            stochastic.qsd_step(st, mdl.jumps, dt, noise[k, b].reshape(-1), fn, chi, 1e-12)
+        C_o, n_o = measure.corr_mps(st, normalize=False)
+        assert _normwise(C_each[b], C_o) < 1e-10
+        assert abs(nrm[b] - n_o) / n_o < 1e-10
+    g.close()
+
+
+def test_qt_batch_matches_oracle_jump_by_jump():
+    L, chi, dt, nsteps, B = 6, 8, 0.05, 12, 6
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    us = tn_inputs.uniforms(77, (nsteps, B))
+    us[:, 0] = 0.001  # force early jumps on trajectory 0
+    fn = _oracle_gate_fn(mdl, "mps")
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ)
+    gj = []
+    for k in range(nsteps):
+        jumped, mask = g.apply_jumps(api.MODE_QT, dt, us[k])
+        gj.append(jumped.copy())
+        g.tebd_step(dt, order=1, mask=mask)
+    _, _, C_each, _ = g.measure_corr(normalize=1, each=True)
+    for b in range(B):
+        st = tebd.product_state(occ, "mps")
+        oj = []
+        for k in range(nsteps):
+            oj.append(stochastic.qt_step(st, mdl, mdl.jumps, dt, us[k, b], fn, chi, 1e-12))
+        assert oj == [int(x[b]) for x in gj]
+        C_o, _ = measure.corr_mps(st, normalize=True)
+        assert _normwise(C_each[b], C_o) < 1e-10
+    assert any(x[0] >= 0 for x in gj)
+    g.close()
+
+
+def test_purified_kraus_matches_oracle():
+    L, chi, chik, dt, nsteps = 4, 32, 4, 0.05, 6
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    dks = [chik if i in (0, L - 1) else 1 for i in range(L)]
+    fn = _oracle_gate_fn(mdl, "purified", dks)
+    st = tebd.product_state(occ, "purified", dk=dks)
+    g = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 1, chi, occ, chi_k_max=chik)
+    for _ in range(nsteps):
+        tebd.trotter_step(st, fn, 1, dt, chi, 1e-12)
+        kraus.kraus_step(st, mdl.jumps, dt, chik)
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_KRAUS, dt)
+    C_o, tr_o = measure.corr_mps(st, normalize=True)
+    C_g, _, _, tr = g.measure_corr()
+    assert _normwise(C_g, C_o) < 1e-10
+    assert abs(tr[0] - tr_o) / tr_o < 1e-10
+    # eig(C) in [0, 1] (rho = XX^+ is a state)
+    ev = np.linalg.eigvalsh((C_g + C_g.conj().T) / 2)
+    assert ev.min() > -1e-10 and ev.max() < 1 + 1e-10
+    g.close()
+
+
+def test_state_roundtrip_and_single_layer_on_random_state():
+    """A random right-isometric state with geometric bond weights (a pre-evolved stand-in):
+    set it, read it back bit-exactly, run one layer, compare the updated bond weights
+    (singular values) and correlations with the oracle on the same input."""
+    L, chi = 10, 16
+    tensors, lams, dims = tn_inputs.random_isometric_mps(5, L, chi)
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 3, chi, tn_inputs.neel(L), sv_cutoff=0.0)
+    g.set_instance(1, tensors, lams, 0.0)
+    t2, l2, ln, _ = g.get_instance(1)
+    for a, b in zip(tensors, t2):
+        assert np.array_equal(a, b)
+    for a, b in zip(lams, l2):
+        assert np.array_equal(a, b)
+    mdl = M.Model(L)
+    st = tebd.TNState(tensors, lams)
+    fn = _oracle_gate_fn(mdl, "mps")
+    gates = {b: fn(b, 0.05) for b in M.layer_bonds(L, 0)}
+    tebd.apply_layer(st, gates, 0, chi, 0.0)
+    # GPU: run a first-order step = layer 0 then layer 1; compare after the full step instead
+    tebd.apply_layer(st, {b: fn(b, 0.05) for b in M.layer_bonds(L, 1)}, 1, chi, 0.0)
+    g.tebd_step(0.05, order=1)
+    t3, l3, ln3, _ = g.get_instance(1)
+    for b in range(L - 1):
+        k = min(len(l3[b]), len(st.lams[b]))
+        assert np.max(np.abs(l3[b][:k] - st.lams[b][:k])) < 1e-10
+    s3 = tebd.TNState(t3, l3, ln3)
+    C_g, _ = measure.corr_mps(s3, normalize=True)
+    C_o, _ = measure.corr_mps(st, normalize=True)
+    assert _normwise(C_g, C_o) < 1e-10
+    g.close()
