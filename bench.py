@@ -1,0 +1,224 @@
+"""Benchmark: batched two-site TEBD updates/s on one MI355X.
+
+Workload (one bench step = one output interval of a quantum-state-diffusion batch):
+  B trajectories of the boundary-driven free-fermion chain (J = 1, gamma = 0.5, source s+ on
+  the first site, sink s- on the last), L = 64 sites, bond dimension chi = 64, SPLIT precision
+  (complex64 MFMA contractions, FP64 Gram/eigensolver/weights/norms); per bench step:
+    INNER first-order Trotter steps (dt = 0.01) of exp(-i h^eff dt) gates, each followed by the
+    diffusion factors 1 + dW sqrt(gamma) L with complex Gaussian dW, then one measurement of
+    C_ij = <c_i^+ c_j> for every trajectory (the output time).
+  Inputs are synthetic and seeded: a right-isometric MPS with geometric bond weights
+  (sigma_a ~ exp(-a/8)) at chi = 64 on every saturated bond stands in for a pre-evolved state.
+Reported: value = two-site updates/s of the batched split path (whole job), the plain
+per-instance FP64 GPU path for comparison, the roofline fraction of the dominant kernel
+(HIP events on the library stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+
+# algorithmic FLOPs per two-site update at the workload shape (m = n = 128, chi_m = k = 64, D = 4)
+def algo_flops(n=128, m=128, chim=64, k=64, D=4):
+    return {
+        "theta": 8.0 * m * n * chim + 8.0 * D * D * (m // 2) * (n // 2),   # Theta GEMM + gate (complex, 8 flops/CMAC)
+        "gram": 8.0 * m * n * (n + 1) / 2,                                 # Hermitian Gram (lower half)
+        "hetrd": 16.0 / 3.0 * n ** 3,                                      # Householder tridiagonalization
+        "vecs": 8.0 * n * n * k,                                           # back-transformation of k vectors
+        "split": 8.0 * m * n * k,                                          # Theta~ V
+    }
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--chi", type=int, default=64)
+    ap.add_argument("--inner", type=int, default=10, help="Trotter steps per output interval")
+    ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--plain-instances", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    return ap.parse_args()
+
+
+def make_state(api, tn_inputs, prec, B, L, chi, seed=2024):
+    model = api.Model.free_fermion(L, 1.0, 0.5)
+    st = api.State(api.KIND_MPS, model, B, chi, tn_inputs.neel(L), precision=prec,
+                   sv_cutoff=1e-6 if prec == api.SPLIT else 1e-12)
+    tensors, lams, dims = tn_inputs.random_isometric_mps(seed, L, chi)
+    st.set_instance(0, tensors, lams, 0.0)
+    if B > 1:
+        st.replicate(0)
+    return st, (tensors, lams)
+
+
+def run_interval(api, st, noise, inner, dt, measure=True):
+    for k in range(inner):
+        st.tebd_step(dt, order=1)
+        st.apply_jumps(api.MODE_QSD, dt, noise[k], api.NOISE_GAUSS)
+    if measure:
+        return st.measure_corr(normalize=0)
+    return None
+
+
+def cpu_baseline(tn_inputs, L, chi, inner, dt, budget_s):
+    """The oracle (numpy complex128, LAPACK SVD) on one trajectory of the same workload."""
+    from oracle import model as M, tebd, stochastic
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    mdl = M.Model(L)
+    cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = M.gate_heff(mdl, b, tau)
+        return cache[(b, tau)]
+    tensors, lams, _ = tn_inputs.random_isometric_mps(2024, L, chi)
+    st = tebd.TNState(tensors, lams)
+    noise = tn_inputs.normals(99, (10 ** 6 // (4 * L) + 8, 4))
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s:
+        stochastic.qsd_step(st, mdl.jumps, dt, noise[steps], fn, chi, 1e-12)
+        steps += 1
+    el = time.perf_counter() - t0
+    upd = steps * (L - 1)
+    return {"value": upd / el, "unit": "two-site updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} Trotter steps (+ diffusion noise) of one L={L} chi={chi} trajectory, "
+                      f"{upd} updates in {el:.1f} s, numpy complex128 + LAPACK SVD"}
+
+
+def oracle_check(api, tn_inputs, st_init, L, chi, inner, dt, noise, C_gpu0):
+    """max |dC| of trajectory 0 after one interval vs the FP64 oracle on the same input."""
+    from oracle import model as M, tebd, stochastic, measure
+    mdl = M.Model(L)
+    cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = M.gate_heff(mdl, b, tau)
+        return cache[(b, tau)]
+    tensors, lams = st_init
+    st = tebd.TNState(tensors, lams)
+    for k in range(inner):
+        stochastic.qsd_step(st, mdl.jumps, dt, noise[k][0:4], fn, chi, 1e-12)
+    C, _ = measure.corr_mps(st, normalize=False)
+    return float(np.max(np.abs(C_gpu0 - C)) / np.max(np.abs(C)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import tn_inputs
+    from paper_2609_18841_amd import api
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    B, L, chi, inner, dt = args.batch, args.L, args.chi, args.inner, args.dt
+    st, init = make_state(api, tn_inputs, api.SPLIT, B, L, chi)
+    total_steps = args.warmup + args.steps
+    noise = tn_inputs.normals(7, (total_steps * inner, B * 2 * 2))
+    print(f"# bench: B={B} L={L} chi={chi} inner={inner} warmup={args.warmup} steps={args.steps}", file=sys.stderr,
+          flush=True)
+
+    err = None
+    for w in range(args.warmup):
+        out = run_interval(api, st, noise[w * inner:(w + 1) * inner], inner, dt, measure=True)
+        if w == 0 and not args.no_check:
+            _, _, _, _ = out
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    st.prof_enable(True)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        i0 = (args.warmup + s) * inner
+        run_interval(api, st, noise[i0:i0 + inner], inner, dt, measure=True)
+        print(f"# step {s} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    updates = args.steps * inner * (L - 1) * B
+    value = updates / el
+    kt = {}
+    for kid, name in enumerate(api.K_NAMES):
+        ms, n = st.prof_query(kid)
+        kt[name] = {"total_ms": ms, "launches": n}
+    st.prof_enable(False)
+
+    # roofline of the dominant update kernel (FLOP-bound, FP64 or FP32 peak by kernel type)
+    fl = algo_flops(n=2 * chi, m=2 * chi, chim=chi, k=chi)
+    upd_kernels = ["theta", "gram", "hetrd", "vecs", "split"]
+    dom = max(upd_kernels, key=lambda k: kt[k]["total_ms"])
+    peak = PEAK["fp32"] if dom in ("theta", "split") else PEAK["fp64"]
+    items_per_launch = updates / max(1, kt[dom]["launches"])
+    avg_s = kt[dom]["total_ms"] / 1e3 / max(1, kt[dom]["launches"])
+    achieved = fl[dom] * items_per_launch / avg_s if avg_s > 0 else 0.0
+    roof = {"bound": "mfma" if dom in ("theta", "split") else "alu", "kernel": dom,
+            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "avg_launch_ms": avg_s * 1e3, "items_per_launch": items_per_launch}
+
+    # plain per-instance FP64 GPU path (one instance per call), same workload shape
+    plain = None
+    if not args.no_plain:
+        del st
+        torch.cuda.empty_cache()
+        pst, _ = make_state(api, tn_inputs, api.FP64, 1, L, chi)
+        pst.tebd_step(dt, order=1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.plain_instances):
+            pst.tebd_step(dt, order=1)
+            pst.apply_jumps(api.MODE_QSD, dt, noise[i][:4], api.NOISE_GAUSS)
+        torch.cuda.synchronize()
+        pel = time.perf_counter() - t1
+        pv = args.plain_instances * (L - 1) / pel
+        plain = {"value": pv, "unit": "two-site updates/s", "precision": "fp64",
+                 "instances_timed": args.plain_instances, "speedup_split_batched": value / pv}
+        del pst
+        torch.cuda.empty_cache()
+
+    if not args.no_check:
+        cst, init2 = make_state(api, tn_inputs, api.SPLIT, 2, L, chi)
+        nz = tn_inputs.normals(7, (inner, B * 2 * 2))[:, :2 * 2 * 2]
+        run_interval(api, cst, nz, inner, dt, measure=False)
+        _, _, Ce, _ = cst.measure_corr(normalize=0, each=True)
+        err = oracle_check(api, tn_inputs, init2, L, chi, inner, dt, nz, Ce[0])
+        del cst
+
+    cpu = None if args.no_cpu else cpu_baseline(tn_inputs, L, chi, inner, dt, args.cpu_seconds)
+    res = {
+        "metric": "two-site TEBD updates/sec (batched trajectories, L=64 chi=64) vs plain, at stated err",
+        "value": value, "unit": "two-site updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c64-contract/f64-svd", "data": "synthetic",
+        "config": {"workload": f"QSD trajectory batch B={B}, L={L}, chi={chi}, dt={dt}, {inner} Trotter steps + "
+                               f"noise per output, 1 measurement of C per output; split precision",
+                   "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner},
+        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain,
+        "err_vs_fp64_oracle": err, "kernel_ms": kt,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

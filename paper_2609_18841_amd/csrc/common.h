@@ -97,6 +97,10 @@ struct DevWork {
     double2* zscratch;           // items * nmax * chi  (global eigenvector scratch, large n)
     double2* pscratch;           // items * nmax*(nmax+1)/2 (packed matrix for large n)
     int* flags;                  // 1 word
+    int* gsz;                    // items  size of the Hermitian eigenproblem (n, or m on the QR route)
+    double2* qra;                // items * nmax * nmax  Householder QR of Theta^+ (FP64 mode, wide items)
+    double2* qtau;               // items * nmax
+    int qr_route;                // 1: wide items (m < n) take the QR route (FP64 mode)
 };
 
 // item -> (instance, bond); returns false for masked items

@@ -23,6 +23,20 @@
 
 __device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1)) / 2 + c; }
 
+// value of v in lane `lane` (uniform index) broadcast to the wave without an LDS round trip
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 64 lanes of a wavefront (every lane receives the total)
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 struct ItemDims { int b, bond, chil, chim, chir, dl, dr, m, n; };
 
 __device__ __forceinline__ bool item_dims(const DevState& s, const DevWork& w, int j, ItemDims& d) {
@@ -100,6 +114,8 @@ __global__ __launch_bounds__(NT) void k_gram(DevState s, DevWork w, int tiles_n)
     __shared__ double2 As[8 * 64], Bs[8 * 64];
     ItemDims d;
     if (!item_dims(s, w, blockIdx.y, d)) return;
+    if (w.qr_route && d.m < d.n) return;  // built by k_qr_wide instead
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.gsz[blockIdx.y] = d.n;
     int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.n || tn * 64 >= d.n || tm < tn) return;  // lower block triangle only
     const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
@@ -115,6 +131,132 @@ __global__ __launch_bounds__(NT) void k_gram(DevState s, DevWork w, int tiles_n)
             return cscale(cconv<double2>(th[(size_t)r * n + c]), wl);
         },
         [&](int i, int c, double2 v) { G[(size_t)i * n + c] = v; }, As, Bs);
+}
+
+
+// ------------------------------------------------------------------ QR route for wide Theta (FP64 mode)
+// For m < n the n x n Gram matrix has rank <= m and its top-m eigenvectors would have to be
+// separated from rounding noise.  Instead: Householder QR  Theta^+ = Q R  (Q = H_0 ... H_{m-1},
+// R m x m), the m x m Hermitian problem  R R^+ = W diag W^+  (the usual eigen pipeline), and
+// V = Q [W; 0], whose columns span the row space of Theta exactly.
+__global__ __launch_bounds__(NT) void k_qr_wide(DevState s, DevWork w) {
+    __shared__ double red[NT / 64];
+    __shared__ double2 sh_tau, sh_sc;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    if (!(d.m < d.n)) return;
+    const int m = d.m, n = d.n, tid = threadIdx.x;
+    const double2* th = reinterpret_cast<const double2*>(w.theta) + (size_t)j * w.theta_stride;
+    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    double2* A = w.qra + (size_t)j * w.nmax * w.nmax;   // n x m, row-major, ld = m
+    double2* qt = w.qtau + (size_t)j * w.nmax;
+    // A[r][c] = conj(Theta[c][r]), Theta = Lambda_left Theta~
+    for (int e = tid; e < n * m; e += NT) {
+        int r = e / m, c = e % m;
+        double wl = lamL ? lamL[c / d.dl] : 1.0;
+        A[e] = cscale(cconj(th[(size_t)c * n + r]), wl);
+    }
+    __syncthreads();
+    for (int jj = 0; jj < m; ++jj) {
+        double p = 0.0;
+        for (int r = jj + 1 + tid; r < n; r += NT) {
+            double2 x = A[(size_t)r * m + jj];
+            p += x.x * x.x + x.y * x.y;
+        }
+        p = wave_sum(p);
+        if ((tid & 63) == 0) red[tid >> 6] = p;
+        __syncthreads();
+        if (tid == 0) {
+            double xn2 = red[0] + red[1] + red[2] + red[3];
+            double2 alpha = A[(size_t)jj * m + jj];
+            double2 t, sc;
+            double beta;
+            if (xn2 == 0.0 && alpha.y == 0.0) {
+                t = mk(0.0, 0.0);
+                beta = alpha.x;
+                sc = mk(1.0, 0.0);
+            } else {
+                double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                t = mk((beta - alpha.x) / beta, -alpha.y / beta);
+                double2 z = mk(alpha.x - beta, alpha.y);
+                double den = z.x * z.x + z.y * z.y;
+                sc = mk(z.x / den, -z.y / den);
+            }
+            sh_tau = t;
+            sh_sc = sc;
+            qt[jj] = t;
+            A[(size_t)jj * m + jj] = mk(beta, 0.0);  // R[jj][jj]; v[0] = 1 is implicit
+        }
+        __syncthreads();
+        const double2 t = sh_tau, sc = sh_sc;
+        for (int r = jj + 1 + tid; r < n; r += NT) A[(size_t)r * m + jj] = cmul(A[(size_t)r * m + jj], sc);
+        __syncthreads();
+        if (t.x != 0.0 || t.y != 0.0) {
+            // A[jj:, c] <- (I - conj(tau) v v^+) A[jj:, c] for c > jj; one thread per column
+            const double2 tc = cconj(t);
+            for (int c = jj + 1 + tid; c < m; c += NT) {
+                double2 acc = A[(size_t)jj * m + c];  // v[0] = 1
+                for (int r = jj + 1; r < n; ++r) cfmac(acc, A[(size_t)r * m + jj], A[(size_t)r * m + c]);
+                acc = cmul(tc, acc);
+                double2 a0 = A[(size_t)jj * m + c];
+                A[(size_t)jj * m + c] = csub(a0, acc);
+                for (int r = jj + 1; r < n; ++r) {
+                    double2 u = cmul(A[(size_t)r * m + jj], acc);
+                    A[(size_t)r * m + c] = csub(A[(size_t)r * m + c], u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // Hermitian problem R R^+ (m x m) into the Gram slot (full matrix)
+    double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+    for (int e = tid; e < m * m; e += NT) {
+        int a = e / m, b2 = e % m;
+        double2 acc = mk(0.0, 0.0);
+        int c0 = a > b2 ? a : b2;
+        for (int c = c0; c < m; ++c) cfmac(acc, A[(size_t)b2 * m + c], A[(size_t)a * m + c]);  // R[a][c] conj(R[b][c])
+        G[(size_t)a * m + b2] = acc;
+    }
+    if (tid == 0) w.gsz[j] = m;
+}
+
+// V = Q [W; 0] for the QR-route items, then B_{bond+1} = V^+
+template <class T>
+__global__ __launch_bounds__(NT) void k_qr_apply(DevState s, DevWork w) {
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    if (!(d.m < d.n)) return;
+    const int m = d.m, n = d.n, tid = threadIdx.x;
+    const int k = w.kout[j];
+    const double2* A = w.qra + (size_t)j * w.nmax * w.nmax;
+    const double2* qt = w.qtau + (size_t)j * w.nmax;
+    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    for (int e = tid; e < (n - m) * k; e += NT) {
+        int r = m + e / k, c = e % k;
+        V[(size_t)r * s.chi + c] = mk(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int jj = m - 1; jj >= 0; --jj) {
+        const double2 t = qt[jj];
+        if (t.x == 0.0 && t.y == 0.0) continue;
+        for (int c = tid; c < k; c += NT) {
+            double2 acc = V[(size_t)jj * s.chi + c];
+            for (int r = jj + 1; r < n; ++r) cfmac(acc, A[(size_t)r * m + jj], V[(size_t)r * s.chi + c]);
+            acc = cmul(t, acc);
+            V[(size_t)jj * s.chi + c] = csub(V[(size_t)jj * s.chi + c], acc);
+            for (int r = jj + 1; r < n; ++r)
+                V[(size_t)r * s.chi + c] = csub(V[(size_t)r * s.chi + c], cmul(A[(size_t)r * m + jj], acc));
+        }
+        __syncthreads();
+    }
+    T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+    for (int e = tid; e < n * k; e += NT) {
+        int c = e / n, r = e % n;
+        Br[e] = cconv<T>(cconj(V[(size_t)r * s.chi + c]));
+    }
 }
 
 // ------------------------------------------------------------------ Householder tridiagonalization
@@ -133,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    const int n = d.n, tid = threadIdx.x;
+    const int n = w.gsz[j], tid = threadIdx.x;
     double2* A = LDS ? packed_lds : (w.pscratch + (size_t)j * (w.nmax * (w.nmax + 1) / 2));
     const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
     double* dd = w.dd + (size_t)j * w.nmax;
@@ -155,14 +297,11 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
             double2 x = A[tri(r, i)];
             part += x.x * x.x + x.y * x.y;
         }
-        red[tid] = part;
+        part = wave_sum(part);
+        if ((tid & 63) == 0) red[tid >> 6] = part;
         __syncthreads();
-        for (int o = NT / 2; o > 0; o >>= 1) {
-            if (tid < o) red[tid] += red[tid + o];
-            __syncthreads();
-        }
         if (tid == 0) {
-            double xn2 = red[0];
+            double xn2 = red[0] + red[1] + red[2] + red[3];
             double2 alpha = A[tri(i + 1, i)];
             double2 t, sc;
             double beta;
@@ -214,14 +353,12 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
             // alpha2 = -1/2 tau (p^+ v)
             double2 part2 = mk(0.0, 0.0);
             for (int r = tid; r < len; r += NT) cfmac(part2, pp[r], vv[r]);
-            redc[tid] = part2;
+            part2.x = wave_sum(part2.x);
+            part2.y = wave_sum(part2.y);
+            if ((tid & 63) == 0) redc[tid >> 6] = part2;
             __syncthreads();
-            for (int o = NT / 2; o > 0; o >>= 1) {
-                if (tid < o) redc[tid] = cadd(redc[tid], redc[tid + o]);
-                __syncthreads();
-            }
             if (tid == 0) {
-                double2 a2 = cmul(t, redc[0]);
+                double2 a2 = cmul(t, cadd(cadd(redc[0], redc[1]), cadd(redc[2], redc[3])));
                 sh_alpha2 = mk(-0.5 * a2.x, -0.5 * a2.y);
             }
             __syncthreads();
@@ -233,15 +370,16 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
             }
             __syncthreads();
             // A22 -= v w^+ + w v^+ (lower triangle)
-            for (int e = tid; e < len * len; e += NT) {
-                int rr = e / len, cc = e % len;
-                if (cc <= rr) {
-                    double2 a = A[tri(i + 1 + rr, i + 1 + cc)];
-                    double2 u1 = cmulc(pp[cc], vv[rr]);  // v_r conj(w_c)
-                    double2 u2 = cmulc(vv[cc], pp[rr]);  // w_r conj(v_c)
+            for (int rr = tid >> 3; rr < len; rr += NT >> 3) {
+                const double2 vr = vv[rr], wr = pp[rr];
+                double2* row = A + tri(i + 1 + rr, i + 1);
+                for (int cc = tid & 7; cc <= rr; cc += 8) {
+                    double2 a = row[cc];
+                    double2 u1 = cmulc(pp[cc], vr);  // v_r conj(w_c)
+                    double2 u2 = cmulc(vv[cc], wr);  // w_r conj(v_c)
                     a.x -= u1.x + u2.x;
                     a.y -= u1.y + u2.y;
-                    A[tri(i + 1 + rr, i + 1 + cc)] = a;
+                    row[cc] = a;
                 }
             }
             __syncthreads();
@@ -253,60 +391,357 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
     }
 }
 
+// Register-resident variant for n <= 128 (512 threads): the full Hermitian matrix is kept in
+// registers, thread t owning row r = t/4 and the 32 columns of block t%4.  Column i of the
+// trailing matrix is read as the conjugate of row i (Hermitian), so no dynamic register
+// indexing is needed; the matrix-vector product reduces over the 4 threads of a row.
+#define HR_N 128
+#define HR_NT 512
+__device__ __forceinline__ double quad_sum(double v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    return v;
+}
+__global__ __launch_bounds__(HR_NT) void k_hetrd_reg(DevState s, DevWork w) {
+    __shared__ double2 rowbuf[HR_N], vv[HR_N], ww[HR_N];
+    __shared__ double redd[HR_NT / 64];
+    __shared__ double2 redc[HR_NT / 64];
+    __shared__ double2 sh_tau, sh_alpha2;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = w.gsz[j], tid = threadIdx.x;
+    const int r = tid >> 2, cb = tid & 3, c0 = cb * 32;
+    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+    double* dd = w.dd + (size_t)j * w.nmax;
+    double* ee = w.ee + (size_t)j * w.nmax;
+    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    double2* tau = w.tau + (size_t)j * w.nmax;
+    // the Gram kernel wrote the lower triangle (and the diagonal blocks); rebuild the full row
+    double2 a[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+        const int c = c0 + t;
+        double2 v = mk(0.0, 0.0);
+        if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
+        a[t] = v;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        // row i of the current matrix -> LDS (its conjugate is column i)
+        if (r == i) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) rowbuf[c0 + t] = a[t];
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // ||x||^2, x = A[i+2.., i] = conj(row i)[i+2..]
+            double p = 0.0;
+            for (int c = i + 2 + tid; c < n; c += 64) {
+                double2 x = rowbuf[c];
+                p += x.x * x.x + x.y * x.y;
+            }
+            p = wave_sum(p);
+            if (tid == 0) {
+                double2 alpha = cconj(rowbuf[i + 1]);
+                double2 t, sc;
+                double beta;
+                if (p == 0.0 && alpha.y == 0.0) {
+                    t = mk(0.0, 0.0);
+                    beta = alpha.x;
+                    sc = mk(1.0, 0.0);
+                } else {
+                    double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
+                    beta = alpha.x >= 0.0 ? -nrm : nrm;
+                    t = mk((beta - alpha.x) / beta, -alpha.y / beta);
+                    double2 z = mk(alpha.x - beta, alpha.y);
+                    double den = z.x * z.x + z.y * z.y;
+                    sc = mk(z.x / den, -z.y / den);
+                }
+                sh_tau = t;
+                dd[i] = rowbuf[i].x;
+                ee[i] = beta;
+                tau[i] = t;
+                sh_alpha2 = sc;  // scale of x, used just below
+            }
+        }
+        __syncthreads();
+        const double2 tv = sh_tau, sc = sh_alpha2;
+        for (int c = i + 1 + tid; c < n; c += HR_NT) {
+            double2 v = (c == i + 1) ? mk(1.0, 0.0) : cmul(cconj(rowbuf[c]), sc);
+            vv[c] = v;
+            refl[(size_t)i * w.nmax + (c - i - 1)] = v;
+        }
+        __syncthreads();
+        if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform
+        // p_r = tau * sum_c A[r][c] v_c over the trailing block
+        double2 acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
+            const int c = c0 + t;
+            if (c > i && c < n) cfma(acc, a[t], vv[c]);
+        }
+        acc.x = quad_sum(acc.x);
+        acc.y = quad_sum(acc.y);
+        if (cb == 0 && r > i && r < n) ww[r] = cmul(tv, acc);
+        __syncthreads();
+        // alpha2 = -1/2 tau (p^+ v)
+        if (tid < 64) {
+            double2 q = mk(0.0, 0.0);
+            for (int c = i + 1 + tid; c < n; c += 64) cfmac(q, ww[c], vv[c]);
+            q.x = wave_sum(q.x);
+            q.y = wave_sum(q.y);
+            if (tid == 0) {
+                double2 a2 = cmul(tv, q);
+                redc[0] = mk(-0.5 * a2.x, -0.5 * a2.y);
+            }
+        }
+        __syncthreads();
+        const double2 a2 = redc[0];
+        // w = p + alpha2 v  (each thread forms the entries it needs)
+        if (r > i && r < n) {
+            double2 vr = vv[r];
+            double2 wr = ww[r];
+            cfma(wr, a2, vr);
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const int c = c0 + t;
+                if (c > i && c < n) {
+                    double2 vc = vv[c];
+                    double2 wc = ww[c];
+                    cfma(wc, a2, vc);
+                    double2 u1 = cmulc(wc, vr);  // v_r conj(w_c)
+                    double2 u2 = cmulc(vc, wr);  // w_r conj(v_c)
+                    a[t].x -= u1.x + u2.x;
+                    a[t].y -= u1.y + u2.y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (r == n - 1) {
+#pragma unroll
+        for (int t = 0; t < 32; ++t)
+            if (c0 + t == n - 1) {
+                dd[n - 1] = a[t].x;
+                ee[n - 1] = 0.0;
+            }
+    }
+}
+
+// Wave-tiled register variant (n <= 128, 512 threads): wave (rh, cb) holds rows rh*64 + lane
+// and the 32 columns of block cb, so whole waves drop out once their rows or columns are
+// reduced (work ~ n^3/3).  Every lane of wave 0 forms the reflector redundantly from a wave
+// reduction (no serial lane), and row sums of the matrix-vector product go through LDS.
+__global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
+    __shared__ double2 rowbuf[HR_N], vv[HR_N], ww[HR_N];
+    __shared__ double2 pbuf[4 * HR_N];
+    __shared__ double2 dotp[2];
+    __shared__ double2 sh_tau;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = w.gsz[j], tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int rh = wv >> 2, cb = wv & 3;
+    const int r = rh * 64 + lane, c0 = cb * 32;
+    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+    double* dd = w.dd + (size_t)j * w.nmax;
+    double* ee = w.ee + (size_t)j * w.nmax;
+    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    double2* tau = w.tau + (size_t)j * w.nmax;
+    double2 a[32];
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+        const int c = c0 + t;
+        double2 v = mk(0.0, 0.0);
+        if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
+        a[t] = v;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        if (r == i) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) rowbuf[c0 + t] = a[t];
+        }
+        __syncthreads();
+        if (wv == 0) {
+            double p = 0.0;
+            for (int c = i + 2 + lane; c < n; c += 64) {
+                double2 x = rowbuf[c];
+                p += x.x * x.x + x.y * x.y;
+            }
+            p = wave_sum(p);
+            const double2 alpha = cconj(rowbuf[i + 1]);
+            double2 tv, sc;
+            double beta;
+            if (p == 0.0 && alpha.y == 0.0) {
+                tv = mk(0.0, 0.0);
+                beta = alpha.x;
+                sc = mk(1.0, 0.0);
+            } else {
+                double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tv = mk((beta - alpha.x) / beta, -alpha.y / beta);
+                double2 z = mk(alpha.x - beta, alpha.y);
+                double den = z.x * z.x + z.y * z.y;
+                sc = mk(z.x / den, -z.y / den);
+            }
+            // vv is zero outside (i, n): the trailing-block loops below need no predicates
+            for (int c = lane; c < HR_N; c += 64) {
+                double2 v = mk(0.0, 0.0);
+                if (c > i && c < n) {
+                    v = (c == i + 1) ? mk(1.0, 0.0) : cmul(cconj(rowbuf[c]), sc);
+                    refl[(size_t)i * w.nmax + (c - i - 1)] = v;
+                }
+                vv[c] = v;
+            }
+            if (lane == 0) {
+                sh_tau = tv;
+                dd[i] = rowbuf[i].x;
+                ee[i] = beta;
+                tau[i] = tv;
+            }
+        }
+        __syncthreads();
+        const double2 tv = sh_tau;
+        if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform
+        const bool rows_live = (rh * 64 + 63 > i) && (rh * 64 < n);
+        const bool cols_live = (c0 + 31 > i) && (c0 < n);
+        // partial p_r over this column block
+        double2 acc = mk(0.0, 0.0);
+        if (rows_live && cols_live) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) cfma(acc, a[t], vv[c0 + t]);
+        }
+        pbuf[cb * HR_N + r] = acc;
+        __syncthreads();
+        // finalize p = tau A v for the rows of this half, and the half's part of p^+ v
+        if (cb == 0) {
+            double2 q = mk(0.0, 0.0);
+            double2 pr = mk(0.0, 0.0);
+            if (r > i && r < n) {
+                pr = cadd(cadd(pbuf[r], pbuf[HR_N + r]), cadd(pbuf[2 * HR_N + r], pbuf[3 * HR_N + r]));
+                pr = cmul(tv, pr);
+                cfmac(q, pr, vv[r]);
+            }
+            ww[r] = pr;  // zero outside (i, n)
+            q.x = wave_sum(q.x);
+            q.y = wave_sum(q.y);
+            if (lane == 0) dotp[rh] = q;
+        }
+        __syncthreads();
+        const double2 a2t = cmul(tv, cadd(dotp[0], dotp[1]));
+        const double2 a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
+        if (rows_live && cols_live && r > i && r < n) {
+            const double2 vr = vv[r];
+            double2 wr = ww[r];
+            cfma(wr, a2, vr);
+            // -conj(v_r), -conj(w_r): a[t] -= v_r conj(w_c) + w_r conj(v_c)  ==  conj(conj(...))
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const double2 vc = vv[c0 + t];
+                double2 wc = ww[c0 + t];
+                cfma(wc, a2, vc);
+                double2 u1 = cmulc(wc, vr);
+                double2 u2 = cmulc(vc, wr);
+                a[t].x -= u1.x + u2.x;
+                a[t].y -= u1.y + u2.y;
+            }
+        }
+    }
+    if (r == n - 1) {
+#pragma unroll
+        for (int t = 0; t < 32; ++t)
+            if (c0 + t == n - 1) {
+                dd[n - 1] = a[t].x;
+                ee[n - 1] = 0.0;
+            }
+    }
+}
+
 // ------------------------------------------------------------------ implicit QL with rotation log
 // Tridiagonal QL with implicit Wilkinson-type shifts (one thread per item).  Every
 // Givens rotation (i, c, s) is logged; the eigenvector matrix is the ordered product
 // Z = G_1 G_2 ... G_N with G acting on columns (i, i+1) as
 //   Z[:,i] <- c Z[:,i] - s Z[:,i+1],  Z[:,i+1] <- s Z[:,i] + c Z[:,i+1].
-__global__ __launch_bounds__(64) void k_steqr(DevState s, DevWork w) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// The working copies of d and e live in LDS (interleaved by lane) when n <= QL_LDS_N.
+#define QL_TPB 32
+#define QL_LDS_N 128
+template <bool LDS>
+__global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
+    __shared__ double sdd[LDS ? QL_LDS_N * QL_TPB : 1], see[LDS ? QL_LDS_N * QL_TPB : 1];
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x * QL_TPB + lane;
     ItemDims dm;
     if (!item_dims(s, w, j, dm)) return;
-    const int n = dm.n;
-    double* d = w.dd + (size_t)j * w.nmax;
-    double* e = w.ee + (size_t)j * w.nmax;
+    const int n = w.gsz[j];
+    double* gd = w.dd + (size_t)j * w.nmax;
+    double* ge = w.ee + (size_t)j * w.nmax;
+    const int st = LDS ? QL_TPB : 1;
+    double* d = LDS ? (sdd + lane) : gd;
+    double* e = LDS ? (see + lane) : ge;
+    if (LDS)
+        for (int i = 0; i < n; ++i) {
+            d[i * st] = gd[i];
+            e[i * st] = ge[i];
+        }
     int* li = w.logi + (size_t)j * w.logcap;
     double2* lcs = w.logcs + (size_t)j * w.logcap;
     const int cap = w.logcap;
     int nr = 0, flag = 0;
-    e[n - 1] = 0.0;
+    e[(n - 1) * st] = 0.0;
     // absolute deflation floor eps*||T||: the Gram matrix fixes its eigenvalues only to that accuracy,
     // and it lets exactly-zero blocks (product states) deflate at once
     double tnorm = 0.0;
-    for (int i = 0; i < n; ++i) tnorm = fmax(tnorm, fabs(d[i]) + fabs(e[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0));
+    for (int i = 0; i < n; ++i)
+        tnorm = fmax(tnorm, fabs(d[i * st]) + fabs(e[i * st]) + (i > 0 ? fabs(e[(i - 1) * st]) : 0.0));
     const double afloor = DBL_EPSILON * tnorm;
     for (int l = 0; l < n; ++l) {
         int iter = 0;
         while (true) {
             int m = l;
             for (; m < n - 1; ++m) {
-                double ddm = fabs(d[m]) + fabs(d[m + 1]);
-                if (fabs(e[m]) <= DBL_EPSILON * ddm || fabs(e[m]) <= afloor) break;
+                double em = fabs(e[m * st]);
+                double ddm = fabs(d[m * st]) + fabs(d[(m + 1) * st]);
+                if (em <= DBL_EPSILON * ddm || em <= afloor) break;
             }
             if (m == l) break;
             if (iter++ >= 60) { flag |= TN_FLAG_NOCONV; break; }
-            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double g = (d[(l + 1) * st] - d[l * st]) / (2.0 * e[l * st]);
             double r = hypot(g, 1.0);
-            g = d[m] - d[l] + e[l] / (g + copysign(r, g));
+            g = d[m * st] - d[l * st] + e[l * st] / (g + copysign(r, g));
             double sn = 1.0, c = 1.0, p = 0.0;
             bool early = false;
+            double dnext = d[m * st];  // d[i+1], carried in a register along the chase
+            double ei_n = e[(m - 1) * st], di_n = d[(m - 1) * st];
             for (int i = m - 1; i >= l; --i) {
-                double f = sn * e[i], bb = c * e[i];
-                r = hypot(f, g);
-                e[i + 1] = r;
-                if (r == 0.0) {
-                    d[i + 1] -= p;
-                    e[m] = 0.0;
+                const double ei = ei_n;
+                const double di = di_n;
+                if (i > l) {  // operands of the next rotation (untouched by this one)
+                    ei_n = e[(i - 1) * st];
+                    di_n = d[(i - 1) * st];
+                }
+                double f = sn * ei, bb = c * ei;
+                const double r2 = f * f + g * g;
+                if (r2 == 0.0) {
+                    e[(i + 1) * st] = 0.0;
+                    d[(i + 1) * st] = dnext - p;
+                    e[m * st] = 0.0;
                     early = true;
                     break;
                 }
-                sn = f / r;
-                c = g / r;
-                g = d[i + 1] - p;
-                r = (d[i] - g) * sn + 2.0 * c * bb;
+                // 1/r from the hardware reciprocal square root plus one Newton step
+                double rinv = __builtin_amdgcn_rsq(r2);
+                rinv = rinv * (1.5 - 0.5 * r2 * rinv * rinv);
+                r = r2 * rinv;
+                e[(i + 1) * st] = r;
+                sn = f * rinv;
+                c = g * rinv;
+                g = dnext - p;
+                r = (di - g) * sn + 2.0 * c * bb;
                 p = sn * r;
-                d[i + 1] = g + p;
+                d[(i + 1) * st] = g + p;
                 g = c * r - bb;
+                dnext = di;
                 if (nr < cap) {
                     li[nr] = i;
                     lcs[nr] = mk(c, sn);
@@ -316,11 +751,13 @@ __global__ __launch_bounds__(64) void k_steqr(DevState s, DevWork w) {
                 ++nr;
             }
             if (early) continue;
-            d[l] -= p;
-            e[l] = g;
-            e[m] = 0.0;
+            d[l * st] -= p;
+            e[l * st] = g;
+            e[m * st] = 0.0;
         }
     }
+    if (LDS)
+        for (int i = 0; i < n; ++i) gd[i] = d[i * st];
     w.nrot[j] = nr < cap ? nr : cap;
     if (flag) atomicOr(w.flags, flag);
 }
@@ -333,7 +770,7 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    const int n = d.n, tid = threadIdx.x;
+    const int n = w.gsz[j], tid = threadIdx.x;
     const double* ev = w.dd + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) lamv[i] = ev[i];
     __syncthreads();
@@ -414,7 +851,7 @@ __global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    const int n = d.n, tid = threadIdx.x;
+    const int n = w.gsz[j], tid = threadIdx.x;
     const int k = w.kout[j];
     const int* sel = w.sel + (size_t)j * w.nmax;
     double2* Z = LDS ? zl : (w.zscratch + (size_t)j * w.nmax * s.chi);
@@ -485,9 +922,121 @@ __global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
         double2 z = Z[e];
         V[(size_t)r * s.chi + c] = z;
     }
-    for (int e = tid; e < n * k; e += NT) {
-        int c = e / n, r = e % n;  // B_{bond+1}[c][r] = conj(V[r][c])
-        Br[e] = cconv<T>(cconj(Z[r * k + c]));
+    if (!(w.qr_route && d.m < d.n))
+        for (int e = tid; e < n * k; e += NT) {
+            int c = e / n, r = e % n;  // B_{bond+1}[c][r] = conj(V[r][c])
+            Br[e] = cconv<T>(cconj(Z[r * k + c]));
+        }
+}
+
+// Fast path for n <= 128 and k <= 64: the rotation replay keeps the row that the next
+// rotation of the same chase needs in a register (a chase touches rows i, i+1, then i+1, i+2,
+// ...), so the dependency chain runs through registers instead of LDS round trips; the real
+// eigenvector block Z (n x k doubles, 64 KB) is the only large LDS buffer, and the
+// Householder back-transformation runs on Z held in registers (4 row groups x 64 columns).
+#define VF_N 128
+#define VF_K 64
+template <class T>
+__global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
+    __shared__ double zr[VF_N * VF_K];
+    __shared__ int lgi[NT];
+    __shared__ double2 lgcs[NT];
+    __shared__ double2 vbuf[VF_N];
+    __shared__ double2 part[NT];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = w.gsz[j], tid = threadIdx.x;
+    const int k = w.kout[j];
+    const int* sel = w.sel + (size_t)j * w.nmax;
+    for (int e = tid; e < n * k; e += NT) zr[e] = (e / k == sel[e % k]) ? 1.0 : 0.0;
+    __syncthreads();
+    {
+        // Replay, newest rotation first; lane c of wave 0 owns column c.  A chase touches rows
+        // (i, i+1), (i+1, i+2), ...: the row shared by consecutive rotations stays in a register.
+        const int nr = w.nrot[j];
+        const int* li = w.logi + (size_t)j * w.logcap;
+        const double2* lcs = w.logcs + (size_t)j * w.logcap;
+        double xr = 0.0;
+        int ci = -1;
+        for (int hi = nr; hi > 0; hi -= NT) {
+            const int lo = hi - NT > 0 ? hi - NT : 0;
+            const int cnt = hi - lo;
+            if (tid < cnt) {
+                lgi[tid] = li[lo + tid];
+                lgcs[tid] = lcs[lo + tid];
+            }
+            __syncthreads();
+            if (tid < k) {
+                for (int q = cnt - 1; q >= 0; --q) {
+                    const int i = lgi[q];
+                    const double cs = lgcs[q].x, sn = lgcs[q].y;
+                    double x;
+                    if (ci == i) {
+                        x = xr;
+                    } else {
+                        if (ci >= 0) zr[ci * k + tid] = xr;
+                        x = zr[i * k + tid];
+                    }
+                    const double y = zr[(i + 1) * k + tid];
+                    zr[i * k + tid] = cs * x + sn * y;
+                    xr = -sn * x + cs * y;
+                    ci = i + 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid < k && ci >= 0) zr[ci * k + tid] = xr;
+    }
+    __syncthreads();
+    const int g = tid >> 6, col = tid & 63;
+    double2 z[VF_N / 4];
+#pragma unroll
+    for (int t = 0; t < VF_N / 4; ++t) {
+        const int r = g + 4 * t;
+        z[t] = (col < k && r < n) ? mk(zr[r * k + col], 0.0) : mk(0.0, 0.0);
+    }
+    const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    const double2* tau = w.tau + (size_t)j * w.nmax;
+    for (int i = n - 2; i >= 0; --i) {
+        const int len = n - 1 - i;
+        const double2 tv = tau[i];
+        if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform across the block
+        __syncthreads();
+        for (int r = tid; r < len; r += NT) vbuf[r] = refl[(size_t)i * w.nmax + r];
+        __syncthreads();
+        double2 acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < VF_N / 4; ++t) {
+            const int r = g + 4 * t;
+            if (r >= i + 1 && r < n) cfmac(acc, vbuf[r - i - 1], z[t]);
+        }
+        part[tid] = acc;
+        __syncthreads();
+        double2 wv = cadd(cadd(part[col], part[64 + col]), cadd(part[128 + col], part[192 + col]));
+        wv = cmul(tv, wv);
+#pragma unroll
+        for (int t = 0; t < VF_N / 4; ++t) {
+            const int r = g + 4 * t;
+            if (r >= i + 1 && r < n) {
+                double2 u = cmul(vbuf[r - i - 1], wv);
+                z[t].x -= u.x;
+                z[t].y -= u.y;
+            }
+        }
+    }
+    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+    const bool wr_br = !(w.qr_route && d.m < d.n);  // the QR route writes B_{bond+1} after expanding V
+    if (col < k) {
+#pragma unroll
+        for (int t = 0; t < VF_N / 4; ++t) {
+            const int r = g + 4 * t;
+            if (r < n) {
+                V[(size_t)r * s.chi + col] = z[t];
+                if (wr_br) Br[(size_t)col * n + r] = cconv<T>(cconj(z[t]));
+            }
+        }
     }
 }
 
@@ -550,22 +1099,31 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
     prof_end(prof, TN_K_THETA, st);
     prof_begin(prof, TN_K_GRAM, st);
     hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_GRAM, st);
     prof_begin(prof, TN_K_HETRD, st);
-    if (w.nmax <= HETRD_LDS_N)
+    if (w.nmax <= HR_N)
+        hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+    else if (w.nmax <= HETRD_LDS_N)
         hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     else
         hipLaunchKernelGGL(k_hetrd<false>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_HETRD, st);
     prof_begin(prof, TN_K_STEQR, st);
-    hipLaunchKernelGGL(k_steqr, dim3((w.nitems + 63) / 64), dim3(64), 0, st, s, w);
+    if (w.nmax <= QL_LDS_N)
+        hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+    else
+        hipLaunchKernelGGL(k_steqr<false>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
     prof_end(prof, TN_K_STEQR, st);
     prof_begin(prof, TN_K_VECS, st);
     hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    if ((size_t)w.nmax * s.chi <= VECS_LDS_ELEMS)
+    if (w.nmax <= VF_N && s.chi <= VF_K)
+        hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    else if ((size_t)w.nmax * s.chi <= VECS_LDS_ELEMS)
         hipLaunchKernelGGL((k_vecs<T, true>), dim3(w.nitems), dim3(NT), 0, st, s, w);
     else
         hipLaunchKernelGGL((k_vecs<T, false>), dim3(w.nitems), dim3(NT), 0, st, s, w);
+    if (w.qr_route) hipLaunchKernelGGL(k_qr_apply<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_VECS, st);
     prof_begin(prof, TN_K_SPLIT, st);
     hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);

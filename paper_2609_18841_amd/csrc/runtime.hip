@@ -67,7 +67,7 @@ struct Layout {
     size_t ws_bytes, total;
     // workspace sub-layout (update)
     size_t u_theta, u_gram, u_refl, u_tau, u_dd, u_ee, u_logi, u_logcs, u_nrot, u_sel, u_kout, u_sout, u_wout, u_V,
-        u_z, u_p, u_bytes;
+        u_z, u_p, u_gsz, u_qra, u_qtau, u_bytes;
     // workspace sub-layout (measurement)
     size_t m_R, m_E, m_X, m_Y, m_W, m_bytes;
 };
@@ -146,6 +146,9 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.u_V = u; u = al(u + (size_t)chunk * nmax * chi * 16);
     ly.u_z = u; if ((size_t)nmax * chi > 8192) u = al(u + (size_t)chunk * nmax * chi * 16);
     ly.u_p = u; if (nmax > 128) u = al(u + (size_t)chunk * ((size_t)nmax * (nmax + 1) / 2) * 16);
+    ly.u_gsz = u; u = al(u + (size_t)chunk * 4);
+    ly.u_qra = u; if (prec == 0) u = al(u + (size_t)chunk * nmax * nmax * 16);
+    ly.u_qtau = u; if (prec == 0) u = al(u + (size_t)chunk * nmax * 16);
     ly.u_bytes = u;
     // measurement workspace
     size_t m = 0;
@@ -581,6 +584,10 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
         w.zscratch = reinterpret_cast<double2*>(ws + s->lay.u_z);
         w.pscratch = reinterpret_cast<double2*>(ws + s->lay.u_p);
         w.flags = at<int>(s, s->lay.off_flags);
+        w.gsz = reinterpret_cast<int*>(ws + s->lay.u_gsz);
+        w.qra = reinterpret_cast<double2*>(ws + s->lay.u_qra);
+        w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
+        w.qr_route = s->prec == 0 ? 1 : 0;
         launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
         HIPCHK(hipGetLastError());
     }
