@@ -94,8 +94,12 @@ def truncation_rank(S, chi_max, cutoff):
     return max(1, min(chi_max, k))
 
 
-def two_site_update(state, b, G, chi_max, cutoff):
-    """Update bond b (sites b, b+1) with gate G in place; return the discarded weight."""
+def two_site_update(state, b, G, chi_max, cutoff, driver="gesdd"):
+    """Update bond b (sites b, b+1) with gate G in place; return the discarded weight.
+
+    driver selects the LAPACK SVD routine ("gesdd", numpy's default, or "gesvd").  Both are
+    exact to rounding; at a binding chi their results differ by the sensitivity of the
+    truncation itself, which is the scale at which truncated runs can be compared (reading C7)."""
     Bl, Br = state.tensors[b], state.tensors[b + 1]
     chil, dl = Bl.shape[0], Bl.shape[1]
     dr, chir = Br.shape[1], Br.shape[2]
@@ -103,7 +107,11 @@ def two_site_update(state, b, G, chi_max, cutoff):
     lam_left = state.lams[b - 1] if b > 0 else np.ones(1)
     Th = lam_left[:, None, None, None] * Tt
     X = Th.reshape(chil * dl, dr * chir)
-    U, S, Vh = np.linalg.svd(X, full_matrices=False)
+    if driver == "gesdd":
+        U, S, Vh = np.linalg.svd(X, full_matrices=False)
+    else:
+        import scipy.linalg
+        U, S, Vh = scipy.linalg.svd(X, full_matrices=False, lapack_driver=driver)
     k = truncation_rank(S, chi_max, cutoff)
     tot = float(np.sum(S ** 2))
     kept = float(np.sum(S[:k] ** 2))

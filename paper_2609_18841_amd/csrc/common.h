@@ -93,14 +93,19 @@ struct DevWork {
     int* kout;                   // items  new bond dimension
     double* sout;                // items  kept norm s
     double* wout;                // items  discarded weight
-    double2* V;                  // items * nmax * chi  (row-major n x k)
-    double2* zscratch;           // items * nmax * chi  (global eigenvector scratch, large n)
+    double2* V;                  // items * nmax * vld  (row-major n x k, leading dimension vld)
+    int vld;                     // chi, or nmax when every eigenvector is formed (Jacobi refinement)
+    double2* zscratch;           // items * nmax * vld  (global eigenvector scratch, large n)
     double2* pscratch;           // items * nmax*(nmax+1)/2 (packed matrix for large n)
     int* flags;                  // 1 word
     int* gsz;                    // items  size of the Hermitian eigenproblem (n, or m on the QR route)
     double2* qra;                // items * nmax * nmax  Householder QR of Theta^+ (FP64 mode, wide items)
     double2* qtau;               // items * nmax
     int qr_route;                // 1: wide items (m < n) take the QR route (FP64 mode)
+    int jacobi;                  // 1: one-sided Jacobi refinement of the SVD (FP64 mode)
+    double2* Y;                  // items * ysz  Y = Theta~ V, column-major m x r (aliases the Gram slot)
+    int ldy;                     // leading dimension of Y (>= mmax)
+    size_t ysz;                  // elements per item
 };
 
 // item -> (instance, bond); returns false for masked items

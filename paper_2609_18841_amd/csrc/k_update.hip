@@ -12,6 +12,8 @@
 //   k_vecs    replay the rotations on the selected unit vectors, back-transform by Q,
 //             store B_{bond+1} <- V^+ (right isometry)
 //   k_split   B_bond <- Theta~ V / s  (Hastings split), dims, log s and weight per item
+// In FP64 mode every eigenvector is formed and a one-sided Jacobi refinement (k_jac_y,
+// k_jacobi, k_select mode 2, k_jac_store) replaces the last two steps.
 // The eigenvalues of H are the squared singular values of Theta = Lambda Theta~ and
 // its eigenvectors the right singular vectors, so this is the truncated SVD of the
 // two-site update computed in FP64 without ever forming U.
@@ -233,29 +235,31 @@ __global__ __launch_bounds__(NT) void k_qr_apply(DevState s, DevWork w) {
     const int k = w.kout[j];
     const double2* A = w.qra + (size_t)j * w.nmax * w.nmax;
     const double2* qt = w.qtau + (size_t)j * w.nmax;
-    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    const int ld = w.vld;
+    double2* V = w.V + (size_t)j * w.nmax * ld;
     for (int e = tid; e < (n - m) * k; e += NT) {
         int r = m + e / k, c = e % k;
-        V[(size_t)r * s.chi + c] = mk(0.0, 0.0);
+        V[(size_t)r * ld + c] = mk(0.0, 0.0);
     }
     __syncthreads();
     for (int jj = m - 1; jj >= 0; --jj) {
         const double2 t = qt[jj];
         if (t.x == 0.0 && t.y == 0.0) continue;
         for (int c = tid; c < k; c += NT) {
-            double2 acc = V[(size_t)jj * s.chi + c];
-            for (int r = jj + 1; r < n; ++r) cfmac(acc, A[(size_t)r * m + jj], V[(size_t)r * s.chi + c]);
+            double2 acc = V[(size_t)jj * ld + c];
+            for (int r = jj + 1; r < n; ++r) cfmac(acc, A[(size_t)r * m + jj], V[(size_t)r * ld + c]);
             acc = cmul(t, acc);
-            V[(size_t)jj * s.chi + c] = csub(V[(size_t)jj * s.chi + c], acc);
+            V[(size_t)jj * ld + c] = csub(V[(size_t)jj * ld + c], acc);
             for (int r = jj + 1; r < n; ++r)
-                V[(size_t)r * s.chi + c] = csub(V[(size_t)r * s.chi + c], cmul(A[(size_t)r * m + jj], acc));
+                V[(size_t)r * ld + c] = csub(V[(size_t)r * ld + c], cmul(A[(size_t)r * m + jj], acc));
         }
         __syncthreads();
     }
+    if (w.jacobi) return;  // V is refined further; B_{bond+1} is written after the Jacobi sweeps
     T* Br = site_ptr<T>(s, d.b, d.bond + 1);
     for (int e = tid; e < n * k; e += NT) {
         int c = e / n, r = e % n;
-        Br[e] = cconv<T>(cconj(V[(size_t)r * s.chi + c]));
+        Br[e] = cconv<T>(cconj(V[(size_t)r * ld + c]));
     }
 }
 
@@ -763,7 +767,12 @@ __global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
 }
 
 // ------------------------------------------------------------------ selection and truncation
-__global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
+// mode 0: Gram eigenvalues (resolution floor rule below), truncate, write Lambda / k / s / weight.
+// mode 1: order all r eigenvalues descending into sel (k = r) and nothing else: the full
+//         eigenbasis that preconditions the Jacobi refinement.
+// mode 2: squared singular values from the Jacobi refinement (resolved to ~eps sigma_0, so the
+//         cutoff applies as stated), truncate and write as in mode 0.
+__global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w, int mode) {
     __shared__ double lamv[512];
     __shared__ double red[NT];
     __shared__ int redi[NT];
@@ -790,7 +799,7 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
     // The Gram route resolves eigenvalues only to ~DBL_EPSILON * lmax (singular values to ~1e-8 sigma_0):
     // a cutoff below that floor cannot be applied faithfully, so every direction is kept (up to chi);
     // discarding a noise-level direction would change the state by up to ~1e-8.
-    const double thr = (s.cutoff2 < 1e-14) ? -1e300 : s.cutoff2 * lmax;
+    const double thr = (mode == 0 && s.cutoff2 < 1e-14) ? -1e300 : s.cutoff2 * lmax;
     int cnt = 0;
     for (int i = tid; i < n; i += NT) cnt += (lamv[i] > thr) ? 1 : 0;
     redi[tid] = cnt;
@@ -801,6 +810,7 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
     k = k < d.m ? k : d.m;
     k = k < n ? k : n;
     if (k < 1) k = 1;
+    if (mode == 1) k = n;
     int* sel = w.sel + (size_t)j * w.nmax;
     double kept_part = 0.0;
     for (int i = tid; i < n; i += NT) {
@@ -816,6 +826,10 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w) {
         }
     }
     __syncthreads();
+    if (mode == 1) {
+        if (tid == 0) w.kout[j] = k;
+        return;
+    }
     red[tid] = kept_part;
     __syncthreads();
     for (int o = NT / 2; o > 0; o >>= 1) { if (tid < o) red[tid] += red[tid + o]; __syncthreads(); }
@@ -854,7 +868,7 @@ __global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
     const int n = w.gsz[j], tid = threadIdx.x;
     const int k = w.kout[j];
     const int* sel = w.sel + (size_t)j * w.nmax;
-    double2* Z = LDS ? zl : (w.zscratch + (size_t)j * w.nmax * s.chi);
+    double2* Z = LDS ? zl : (w.zscratch + (size_t)j * w.nmax * w.vld);
     for (int e = tid; e < n * k; e += NT) {
         int r = e / k, c = e % k;
         Z[e] = mk(r == sel[c] ? 1.0 : 0.0, 0.0);
@@ -915,14 +929,14 @@ __global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
         }
     }
     // ---- outputs
-    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    double2* V = w.V + (size_t)j * w.nmax * w.vld;
     T* Br = site_ptr<T>(s, d.b, d.bond + 1);
     for (int e = tid; e < n * k; e += NT) {
         int r = e / k, c = e % k;
         double2 z = Z[e];
-        V[(size_t)r * s.chi + c] = z;
+        V[(size_t)r * w.vld + c] = z;
     }
-    if (!(w.qr_route && d.m < d.n))
+    if (!(w.qr_route && d.m < d.n) && !w.jacobi)
         for (int e = tid; e < n * k; e += NT) {
             int c = e / n, r = e % n;  // B_{bond+1}[c][r] = conj(V[r][c])
             Br[e] = cconv<T>(cconj(Z[r * k + c]));
@@ -1025,15 +1039,16 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
             }
         }
     }
-    double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    double2* V = w.V + (size_t)j * w.nmax * w.vld;
     T* Br = site_ptr<T>(s, d.b, d.bond + 1);
-    const bool wr_br = !(w.qr_route && d.m < d.n);  // the QR route writes B_{bond+1} after expanding V
+    // the QR route writes B_{bond+1} after expanding V, the Jacobi refinement after its sweeps
+    const bool wr_br = !(w.qr_route && d.m < d.n) && !w.jacobi;
     if (col < k) {
 #pragma unroll
         for (int t = 0; t < VF_N / 4; ++t) {
             const int r = g + 4 * t;
             if (r < n) {
-                V[(size_t)r * s.chi + col] = z[t];
+                V[(size_t)r * w.vld + col] = z[t];
                 if (wr_br) Br[(size_t)col * n + r] = cconv<T>(cconj(z[t]));
             }
         }
@@ -1059,15 +1074,186 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     if (tm * 64 >= d.m || tn * 64 >= k) return;
     typedef typename real_of<T>::type R;
     const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)j * w.theta_stride;
-    const double2* V = w.V + (size_t)j * w.nmax * s.chi;
+    const double2* V = w.V + (size_t)j * w.nmax * w.vld;
     T* Bl = site_ptr<T>(s, d.b, d.bond);
-    const int n = d.n, chi = s.chi;
+    const int n = d.n, chi = w.vld;
     const R inv = (R)(1.0 / sv);
     block_gemm<T, true, true, 8>(
         d.m, k, n, tm * 64, tn * 64,
         [&](int r, int q) { return th[(size_t)r * n + q]; },
         [&](int q, int c) { return cconv<T>(V[(size_t)q * chi + c]); },
         [&](int r, int c, T v) { Bl[(size_t)r * k + c] = cscale(v, inv); }, As, Bs);
+}
+
+// ------------------------------------------------------------------ FP64 mode: one-sided Jacobi refinement
+// The Gram eigenvalues carry an absolute error of ~eps * sigma_0^2, so singular values below
+// ~sqrt(eps) sigma_0 (~1e-8 sigma_0) are not resolved, and a truncation among them would be
+// decided by rounding.  In FP64 mode every Gram eigenvector is formed (V, n x r), and the columns
+// of Y = Theta~ V are made orthogonal in the Lambda_{bond-1}^2-weighted inner product by one-sided
+// (Hestenes) Jacobi rotations applied to Y and V alike.  The singular values of Theta are then
+// the weighted column norms of Y, resolved to ~eps sigma_0, and Y itself is Theta~ V for the
+// Hastings split.  The Gram basis leaves only clusters of nearly equal small singular values to
+// rotate, so a few sweeps converge.
+__global__ __launch_bounds__(NT) void k_jac_y(DevState s, DevWork w, int tiles_n) {
+    __shared__ double2 As[8 * 64], Bs[8 * 64];
+    ItemDims d;
+    const int j = blockIdx.y;
+    if (!item_dims(s, w, j, d)) return;
+    const int r = w.kout[j];
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= d.m || tn * 64 >= r) return;
+    const double2* th = reinterpret_cast<const double2*>(w.theta) + (size_t)j * w.theta_stride;
+    const double2* V = w.V + (size_t)j * w.nmax * w.vld;
+    double2* Y = w.Y + (size_t)j * w.ysz;
+    const int n = d.n, ld = w.vld, ldy = w.ldy;
+    block_gemm<double2, true, true, 8>(
+        d.m, r, n, tm * 64, tn * 64,
+        [&](int i, int q) { return th[(size_t)i * n + q]; },
+        [&](int q, int c) { return V[(size_t)q * ld + c]; },
+        [&](int i, int c, double2 v) { Y[(size_t)c * ldy + i] = v; }, As, Bs);
+}
+
+#define JAC_NT 512
+#define JAC_SWEEPS 30
+// One workgroup per item.  Sweeps follow a round-robin tournament over the r columns (column 0
+// fixed, the others rotating; one bye when r is odd): each round is a set of disjoint pairs, one
+// wavefront per pair, so rounds need only a barrier between them.  A pair is rotated when its
+// weighted cosine exceeds eps*sqrt(m) and both columns are above the rounding floor
+// (eps^2 * sum of all squared norms); the sweeps stop when a sweep rotates nothing.
+__global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
+    __shared__ double wt[512];
+    __shared__ double redv[JAC_NT / 64];
+    __shared__ int rotated;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int m = d.m, n = d.n, r = w.kout[j], tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int NW = JAC_NT / 64;
+    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    for (int i = tid; i < m; i += JAC_NT) {
+        const double l = lamL ? lamL[i / d.dl] : 1.0;
+        wt[i] = l * l;
+    }
+    __syncthreads();
+    double2* Y = w.Y + (size_t)j * w.ysz;
+    double2* V = w.V + (size_t)j * w.nmax * w.vld;
+    const int ldy = w.ldy, ld = w.vld;
+    double p = 0.0;
+    for (int c = wv; c < r; c += NW)
+        for (int i = lane; i < m; i += 64) {
+            const double2 y = Y[(size_t)c * ldy + i];
+            p += wt[i] * (y.x * y.x + y.y * y.y);
+        }
+    p = wave_sum(p);
+    if (lane == 0) redv[wv] = p;
+    __syncthreads();
+    double total = 0.0;
+    for (int q = 0; q < NW; ++q) total += redv[q];
+    const double floor2 = DBL_EPSILON * DBL_EPSILON * total;
+    const double tol = DBL_EPSILON * sqrt((double)m);
+    const int R = r + (r & 1);
+    int sweep = 0;
+    for (; sweep < JAC_SWEEPS; ++sweep) {
+        if (tid == 0) rotated = 0;
+        __syncthreads();
+        int any = 0;
+        for (int t = 0; t < R - 1; ++t) {
+            for (int pi = wv; pi < R / 2; pi += NW) {
+                int a, b;
+                if (pi == 0) {
+                    a = 0;
+                    b = 1 + t % (R - 1);
+                } else {
+                    a = 1 + (t + pi) % (R - 1);
+                    b = 1 + (t - pi + (R - 1)) % (R - 1);
+                }
+                if (a > b) { const int x = a; a = b; b = x; }
+                if (b >= r) continue;  // bye
+                double2* yp = Y + (size_t)a * ldy;
+                double2* yq = Y + (size_t)b * ldy;
+                double app = 0.0, aqq = 0.0, cx = 0.0, cy = 0.0;
+                for (int i = lane; i < m; i += 64) {
+                    const double2 u = yp[i], v = yq[i];
+                    const double ww = wt[i];
+                    app += ww * (u.x * u.x + u.y * u.y);
+                    aqq += ww * (v.x * v.x + v.y * v.y);
+                    cx += ww * (u.x * v.x + u.y * v.y);
+                    cy += ww * (u.x * v.y - u.y * v.x);
+                }
+                app = wave_sum(app);
+                aqq = wave_sum(aqq);
+                cx = wave_sum(cx);
+                cy = wave_sum(cy);
+                const double g = sqrt(cx * cx + cy * cy);
+                if (!(app > floor2 && aqq > floor2) || !(g > tol * sqrt(app * aqq))) continue;
+                // rotate (p, q~ = conj(ph) q), ph = c/|c|, by the real Jacobi angle of [[app, g], [g, aqq]]
+                const double zeta = (aqq - app) / (2.0 * g);
+                const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                const double2 ph = mk(cx / g, cy / g), phc = mk(cx / g, -cy / g);
+                for (int i = lane; i < m; i += 64) {
+                    const double2 u = yp[i], v = yq[i];
+                    const double2 cv = cmul(phc, v), pu = cmul(ph, u);
+                    yp[i] = mk(cs * u.x - sn * cv.x, cs * u.y - sn * cv.y);
+                    yq[i] = mk(sn * pu.x + cs * v.x, sn * pu.y + cs * v.y);
+                }
+                for (int q = lane; q < n; q += 64) {
+                    const double2 u = V[(size_t)q * ld + a], v = V[(size_t)q * ld + b];
+                    const double2 cv = cmul(phc, v), pu = cmul(ph, u);
+                    V[(size_t)q * ld + a] = mk(cs * u.x - sn * cv.x, cs * u.y - sn * cv.y);
+                    V[(size_t)q * ld + b] = mk(sn * pu.x + cs * v.x, sn * pu.y + cs * v.y);
+                }
+                any = 1;
+            }
+            __syncthreads();
+        }
+        if (any) rotated = 1;
+        __syncthreads();
+        const int done = !rotated;
+        __syncthreads();
+        if (done) break;
+    }
+    if (sweep == JAC_SWEEPS && tid == 0) atomicOr(w.flags, TN_FLAG_NOCONV);
+    // squared singular values = weighted column norms (into the eigenvalue slot for k_select)
+    for (int c = wv; c < r; c += NW) {
+        double q2 = 0.0;
+        for (int i = lane; i < m; i += 64) {
+            const double2 y = Y[(size_t)c * ldy + i];
+            q2 += wt[i] * (y.x * y.x + y.y * y.y);
+        }
+        q2 = wave_sum(q2);
+        if (lane == 0) w.dd[(size_t)j * w.nmax + c] = q2;
+    }
+}
+
+// B_bond = Y[:, sel] / s (= Theta~ V / s), B_{bond+1} = V[:, sel]^+, dims, log s and weight per item
+template <class T>
+__global__ __launch_bounds__(NT) void k_jac_store(DevState s, DevWork w, double* glog, double* gwt) {
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int k = w.kout[j], m = d.m, n = d.n, tid = threadIdx.x;
+    const double sv = w.sout[j];
+    if (tid == 0) {
+        s.dims[(size_t)d.b * (s.L + 1) + d.bond + 1] = k;
+        const int g = w.item0 + j;
+        glog[g] = log(sv);
+        gwt[g] = w.wout[j];
+    }
+    const int* sel = w.sel + (size_t)j * w.nmax;
+    const double2* Y = w.Y + (size_t)j * w.ysz;
+    const double2* V = w.V + (size_t)j * w.nmax * w.vld;
+    T* Bl = site_ptr<T>(s, d.b, d.bond);
+    T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+    const double inv = 1.0 / sv;
+    for (int e = tid; e < m * k; e += NT) {
+        const int i = e / k, c = e % k;
+        Bl[e] = cconv<T>(cscale(Y[(size_t)sel[c] * w.ldy + i], inv));
+    }
+    for (int e = tid; e < k * n; e += NT) {
+        const int c = e / n, q = e % n;
+        Br[e] = cconv<T>(cconj(V[(size_t)q * w.vld + sel[c]]));
+    }
 }
 
 // per instance: add the log-norms and discarded weights of its items (fixed order)
@@ -1116,17 +1302,25 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
         hipLaunchKernelGGL(k_steqr<false>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
     prof_end(prof, TN_K_STEQR, st);
     prof_begin(prof, TN_K_VECS, st);
-    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    if (w.nmax <= VF_N && s.chi <= VF_K)
+    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, w.jacobi ? 1 : 0);
+    if (w.nmax <= VF_N && w.vld <= VF_K)
         hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    else if ((size_t)w.nmax * s.chi <= VECS_LDS_ELEMS)
+    else if ((size_t)w.nmax * w.vld <= VECS_LDS_ELEMS)
         hipLaunchKernelGGL((k_vecs<T, true>), dim3(w.nitems), dim3(NT), 0, st, s, w);
     else
         hipLaunchKernelGGL((k_vecs<T, false>), dim3(w.nitems), dim3(NT), 0, st, s, w);
     if (w.qr_route) hipLaunchKernelGGL(k_qr_apply<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_VECS, st);
     prof_begin(prof, TN_K_SPLIT, st);
-    hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+    if (w.jacobi) {
+        const int tr = (w.nmax + 63) / 64;
+        hipLaunchKernelGGL(k_jac_y, dim3(tm * tr, w.nitems), dim3(NT), 0, st, s, w, tr);
+        hipLaunchKernelGGL(k_jacobi, dim3(w.nitems), dim3(JAC_NT), 0, st, s, w);
+        hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 2);
+        hipLaunchKernelGGL(k_jac_store<T>, dim3(w.nitems), dim3(NT), 0, st, s, w, glog, gwt);
+    } else {
+        hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+    }
     prof_end(prof, TN_K_SPLIT, st);
 }
 

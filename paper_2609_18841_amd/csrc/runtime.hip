@@ -143,8 +143,10 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.u_kout = u; u = al(u + (size_t)chunk * 4);
     ly.u_sout = u; u = al(u + (size_t)chunk * 8);
     ly.u_wout = u; u = al(u + (size_t)chunk * 8);
-    ly.u_V = u; u = al(u + (size_t)chunk * nmax * chi * 16);
-    ly.u_z = u; if ((size_t)nmax * chi > 8192) u = al(u + (size_t)chunk * nmax * chi * 16);
+    // FP64 mode forms every eigenvector (Jacobi refinement): V is n x n there, n x chi otherwise
+    const size_t vld = prec == 0 ? (size_t)nmax : (size_t)chi;
+    ly.u_V = u; u = al(u + (size_t)chunk * nmax * vld * 16);
+    ly.u_z = u; if ((size_t)nmax * vld > 8192) u = al(u + (size_t)chunk * nmax * vld * 16);
     ly.u_p = u; if (nmax > 128) u = al(u + (size_t)chunk * ((size_t)nmax * (nmax + 1) / 2) * 16);
     ly.u_gsz = u; u = al(u + (size_t)chunk * 4);
     ly.u_qra = u; if (prec == 0) u = al(u + (size_t)chunk * nmax * nmax * 16);
@@ -540,7 +542,7 @@ static int check_flags(tn_state* s) {
         HIPCHK(hipMemsetAsync(s->arena + s->lay.off_flags, 0, 4, s->stream));
         if (flags & TN_FLAG_NAN) return fail(TN_ENUMERIC, "NaN in a two-site update");
         if (flags & TN_FLAG_LOGFULL) return fail(TN_ENOCONV, "rotation log capacity exceeded");
-        if (flags & TN_FLAG_NOCONV) return fail(TN_ENOCONV, "tridiagonal QL did not converge");
+        if (flags & TN_FLAG_NOCONV) return fail(TN_ENOCONV, "tridiagonal QL or Jacobi sweeps did not converge");
     }
     return TN_OK;
 }
@@ -588,6 +590,11 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
         w.qra = reinterpret_cast<double2*>(ws + s->lay.u_qra);
         w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
         w.qr_route = s->prec == 0 ? 1 : 0;
+        w.jacobi = s->prec == 0 ? 1 : 0;
+        w.vld = s->prec == 0 ? s->nmax : s->chi;
+        w.Y = w.gram;  // the Gram slot is free once the Householder reduction has read it
+        w.ldy = s->nmax;
+        w.ysz = (size_t)s->nmax * s->nmax;
         launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
         HIPCHK(hipGetLastError());
     }
