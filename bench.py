@@ -25,6 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
+# rocprofv3 counter summary that holds the HBM bytes per dispatch of each update kernel at this
+# workload's launch shape (8192 / 7936 updates per dispatch); it names the sha256 of the kernel
+# sources it was taken with, and its figures are used only while the sources still match.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_qsd_B256_L64_chi64_split.txt")
+# timing bucket -> the kernel that runs in it for this workload (split precision, n = 128, chi = 64)
+BUCKET_KERNEL = {"gram": "k_gram", "hetrd": "k_hetrd_tile", "vecs": "k_vecs_fast", "split": "k_split"}
 
 # algorithmic FLOPs per two-site update at the workload shape (m = n = 128, chi_m = k = 64, D = 4)
 def algo_flops(n=128, m=128, chim=64, k=64, D=4):
@@ -35,6 +41,32 @@ def algo_flops(n=128, m=128, chim=64, k=64, D=4):
         "vecs": 8.0 * n * n * k,                                           # back-transformation of k vectors
         "split": 8.0 * m * n * k,                                          # Theta~ V
     }
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken with different kernel sources."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    src = [ln for ln in lines if ln.startswith("# sources:")]
+    if not src:
+        return None
+    for item in src[0][len("# sources:"):].split(","):
+        name, h = item.strip().split(" sha256:")
+        path = os.path.join(ROOT, "paper_2609_18841_amd", "csrc", name)
+        if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] != h:
+            return None
+    for ln in lines:
+        if ln.startswith("#"):
+            continue
+        parts = ln.split()
+        nm = " ".join(parts[:-3]).replace("void ", "").split("<")[0].strip()
+        if nm == kernel:
+            return float(parts[-1])
+    return None
 
 
 def parse():
@@ -52,6 +84,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -134,6 +168,17 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calib_copy > 0:
+        # reference traffic for the FETCH_SIZE / WRITE_SIZE counters: each copy reads and writes
+        # exactly MIB MiB
+        nb = args.calib_copy << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nb, "copies": 3}))
+        return
     B, L, chi, inner, dt = args.batch, args.L, args.chi, args.inner, args.dt
     st, init = make_state(api, tn_inputs, api.SPLIT, B, L, chi)
     total_steps = args.warmup + args.steps
@@ -173,9 +218,11 @@ def main():
     items_per_launch = updates / max(1, kt[dom]["launches"])
     avg_s = kt[dom]["total_ms"] / 1e3 / max(1, kt[dom]["launches"])
     achieved = fl[dom] * items_per_launch / avg_s if avg_s > 0 else 0.0
-    roof = {"bound": "mfma" if dom in ("theta", "split") else "alu", "kernel": dom,
+    kname = BUCKET_KERNEL.get(dom, dom)
+    roof = {"bound": "mfma" if dom in ("theta", "split") else "alu", "kernel": kname,
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "avg_launch_ms": avg_s * 1e3, "items_per_launch": items_per_launch}
+            "traffic": profiled_traffic(kname), "traffic_unit": "bytes per launch",
+            "algo_flops_per_update": fl[dom], "avg_launch_ms": avg_s * 1e3, "items_per_launch": items_per_launch}
 
     # plain per-instance FP64 GPU path (one instance per call), same workload shape
     plain = None

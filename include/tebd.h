@@ -161,7 +161,7 @@ int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 #define TN_K_THETA   0  /* Theta formation + gate */
 #define TN_K_GRAM    1  /* weighted Gram matrix */
 #define TN_K_HETRD   2  /* Householder tridiagonalization */
-#define TN_K_STEQR   3  /* tridiagonal QL eigenvalues */
+#define TN_K_STEQR   3  /* tridiagonal QL eigenvalues + truncation rank selection */
 #define TN_K_VECS    4  /* eigenvectors: rotations + back-transformation */
 #define TN_K_SPLIT   5  /* split / store */
 #define TN_K_MEASURE 6  /* measurement sweep */

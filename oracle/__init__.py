@@ -10,7 +10,7 @@ to Matrix Product State algorithms for the integration of Lindblad equation"):
 plain loops, numpy/scipy library primitives (matmul, SVD, eigh, expm,
 Sylvester solver), complex128 throughout, no blocking or fusion beyond what the
 paper's definitions state.  Each function cites the section/equation it
-follows.  Readings of ambiguous or garbled passages are listed in the design doc.
+follows, and states how it reads a passage where the paper is ambiguous or garbled.
 
 Modules
 -------

@@ -2,7 +2,7 @@
 
 Oracle (test infrastructure).  Sec. 1 eq. (Lindblad) written with genuine
 fermionic operators built by the Jordan-Wigner map of Sec. 2.1 (so the sink
-L2 = c_N carries its string here; this is what pins reading C3), vectorized
+L2 = c_N carries its string here, which pins dropping it in the local model), vectorized
 with the row-major map of eq. (Choi): A rho B -> A (x) B^T.
 """
 import numpy as np

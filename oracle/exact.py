@@ -4,7 +4,7 @@ Oracle (test infrastructure).  Sec. 2.1: C_ij = <c_i^+ c_j> obeys the closed
 linear equation (eqCorr) dC/dt = -i K C + i C K^+ + Gamma with
 K = J A - (i gamma/2)(P_1 + P_N) (A: nearest-neighbour adjacency, P_k the
 projector on site k; the paper's delta_{N,1} delta_{j,N} is read as
-delta_{i,N} delta_{j,N}, reading C1) and Gamma = gamma e_1 e_1^T.  Its solution is
+delta_{i,N} delta_{j,N}, the only reading consistent with eq. LindbladEff) and Gamma = gamma e_1 e_1^T.  Its solution is
 eq. (SoleqCorr).
 """
 import numpy as np

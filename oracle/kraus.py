@@ -4,7 +4,8 @@ Oracle (test infrastructure).  Sec. 3.2: the jump part of the first-order
 splitting acts on rho = X X^+ as rho -> rho + gamma dt L rho L^+ (the
 factor (1 + gamma_i dt L_i (x) L_i^+)), i.e. on the site tensor through
     R = sum_k [A^k (A^k)^+ + gamma dt (L A^k)(L A^k)^+]     (eq. MatrixR, with the
-                                                            gamma dt factor: reading C9)
+                                                            gamma dt factor, which the printed
+                                                            eq. MatrixR lacks)
 followed by the diagonalization R = sum lambda |phi><phi| and
 A^{k} <- sqrt(lambda_k) phi_k for the chi_k largest lambda (eq. NewPurified).
 
@@ -12,7 +13,7 @@ The paper's local R assumes the rest of the network acts as the identity on
 the site's bond indices (the site is the orthogonality centre).  In the
 Hastings form used here every tensor right of a bond is a right isometry and
 the left environment of site s is diag(Lambda_{s-1}^2), so the eigenproblem is
-posed for Lambda_{s-1} A (reading C9b); the new tensor is then taken as M W
+posed for Lambda_{s-1} A (the site tensor weighted by its environment); the new tensor is then taken as M W
 (no Lambda^{-1}), exactly like the Hastings two-site split.
 
 Two routes are implemented:

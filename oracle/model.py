@@ -4,7 +4,9 @@ Oracle (test infrastructure).  Sec. 2.1 eq. (Hamiltonian): H = -J sum_i
 (c_{i+1}^+ c_i + c_i^+ c_{i+1}); jump operators L1 = c_1^+ (source on the first
 site) and L2 = c_N (sink on the last site), both with rate gamma.  Under the
 Jordan-Wigner map the bond term is -J (s+ s- + s- s+) and L1 = s+_1; the string
-carried by L2 is dropped (reading C3 in the design doc), so L2 = s-_N.
+carried by L2 is dropped, so L2 = s-_N: for states block-diagonal in the particle
+number (the dynamics keep them so) the string only changes a sign that cancels in
+L rho L^+ (the exact integration in ed.py keeps the string and pins this).
 
 Local basis |0> (empty), |1> (occupied); matrices are [out, in].
 Two-site index: n_i * d + n_{i+1}.  Sites are 0-based here.
@@ -70,7 +72,7 @@ class Model:
 
         Sec. 3.1 eq. (Liouvillian) with the row-major map rho_ij -> |i>(x)|j> of eq. (Choi):
         A rho B -> A (x) B^T, hence L rho L^+ -> L (x) L^*, 1 (x) H^T and 1 (x) (L^+L)^T
-        (reading C2).  Dissipators are split over bonds like the effective Hamiltonian.
+        (the paper prints L (x) L^+ and 1 (x) H, which break the trace).  Dissipators are split over bonds like the effective Hamiltonian.
         Returned as a 16x16 matrix in the basis (m_b, m_{b+1}) = ((n_b, n'_b), (n_{b+1}, n'_{b+1})).
         """
         h = self.h_bond(b)
@@ -128,7 +130,7 @@ def layer_bonds(L, parity):
     """Bonds of one Trotter layer, named by their left site (0-based).
 
     parity 0: bonds (0,1),(2,3),... = the paper's odd bonds (1-based left site odd).
-    parity 1: bonds (1,2),(3,4),... = the paper's even bonds.  Sec. 2.3 (reading C13).
+    parity 1: bonds (1,2),(3,4),... = the paper's even bonds.  Sec. 2.3.
     """
     return list(range(parity, L - 1, 2))
 

@@ -3,7 +3,7 @@
 Oracle (test infrastructure).  Random numbers are inputs (FP64), so the HIP
 path can be compared draw for draw.
 
-Quantum trajectories, Sec. 4.1 (reading C10): per time step, with the current
+Quantum trajectories, Sec. 4.1: per time step, with the current
 state normalized, the jump probabilities are p_k = gamma_k dt <L_k^+ L_k>
 (eq. TransitionRate times dt).  One uniform u in [0,1) picks jump k if
 sum_{k'<k} p_k' <= u < sum_{k'<=k} p_k'; the jumped state is L_k psi, renormalized.

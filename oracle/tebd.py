@@ -15,13 +15,14 @@ ThetaPurified):
     Theta(n_L = (a,p'), n_R = (q',c)) = U S V^+          (SVD)
     keep k = min(chi_max, #{S_a > cutoff * S_0}) singular values
     discarded weight = sum_{a>=k} S_a^2 / sum_a S_a^2       (eq. HilbertSchmidtNorm,
-                                                          eq. TruncationErr read as in C7)
+                                                          eq. TruncationErr without its typos)
     s = (sum_{a<k} S_a^2)^{1/2}
     B_{i+1} <- V^+[:k]                   (right isometry)
     B_i     <- Theta~ V[:, :k] / s       (Hastings: no Lambda^{-1})
     Lambda_i <- S[:k] / s,  lognorm += log s
 The state is never renormalized (the scale goes to lognorm), which is what the
-non-hermitian and Liouvillian evolutions of Sec. 3 and 4 require (reading C8).
+non-hermitian and Liouvillian evolutions of Sec. 3 and 4 require: for a vectorized
+density matrix sum Lambda^2 is Tr rho^2, not Tr rho.
 """
 import numpy as np
 
@@ -87,7 +88,7 @@ def theta_tilde(Bl, Br, G):
 
 
 def truncation_rank(S, chi_max, cutoff):
-    """Rule of reading C7: k = min(chi_max, #{S_a > cutoff*S_0}), at least 1."""
+    """k = min(chi_max, #{S_a > cutoff*S_0}), at least 1 (descending order, no multiplet protection)."""
     if S.size == 0 or S[0] <= 0.0:
         return 1
     k = int(np.count_nonzero(S > cutoff * S[0]))
@@ -99,7 +100,7 @@ def two_site_update(state, b, G, chi_max, cutoff, driver="gesdd"):
 
     driver selects the LAPACK SVD routine ("gesdd", numpy's default, or "gesvd").  Both are
     exact to rounding; at a binding chi their results differ by the sensitivity of the
-    truncation itself, which is the scale at which truncated runs can be compared (reading C7)."""
+    truncation itself, which is the scale at which truncated runs can be compared."""
     Bl, Br = state.tensors[b], state.tensors[b + 1]
     chil, dl = Bl.shape[0], Bl.shape[1]
     dr, chir = Br.shape[1], Br.shape[2]

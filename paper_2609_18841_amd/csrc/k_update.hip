@@ -1300,9 +1300,9 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
         hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
     else
         hipLaunchKernelGGL(k_steqr<false>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, w.jacobi ? 1 : 0);
     prof_end(prof, TN_K_STEQR, st);
     prof_begin(prof, TN_K_VECS, st);
-    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, w.jacobi ? 1 : 0);
     if (w.nmax <= VF_N && w.vld <= VF_K)
         hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     else if ((size_t)w.nmax * w.vld <= VECS_LDS_ELEMS)

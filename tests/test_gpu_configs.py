@@ -65,7 +65,7 @@ def test_mpdo_config1_against_oracle_and_exact():
     chi=64 binds from about t=0.4 on (the middle cut reaches operator rank 256).  Once it binds,
     the truncated state depends on rounding inside the SVD: two LAPACK drivers (gesdd, gesvd) run
     through the oracle differ by 1e-10 at t=0.4, 1e-9 at t=0.8 and 3e-4 from t=1.2 on.  The GPU
-    is compared with the gesdd oracle after every 8 steps at that scale (reading C7); the distance
+    is compared with the gesdd oracle after every 8 steps at that scale; the distance
     to the exact solution is the truncation error both carry (about 2e-2 at t=2)."""
     from oracle import tebd as OT, measure as OM
     L, chi, dt, T = 8, 64, 0.05, 2.0

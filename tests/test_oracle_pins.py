@@ -282,18 +282,22 @@ def _traj_average(kind, ntraj, L, T, dt, seed):
                 stochastic.qt_step(st, mdl, mdl.jumps, dt, us[k], fn, 32, 1e-12)
             C, n2 = measure.corr_mps(st, normalize=True)
         else:
-            rn = rng.standard_normal((nsteps, 4))
+            if kind == "qsd":
+                rn, nk = rng.standard_normal((nsteps, 4)), "gauss"
+            else:
+                rn, nk = rng.random((nsteps, 2)), "binary"
             for k in range(nsteps):
-                stochastic.qsd_step(st, mdl.jumps, dt, rn[k], fn, 32, 1e-12)
+                stochastic.qsd_step(st, mdl.jumps, dt, rn[k], fn, 32, 1e-12, noise_kind=nk)
             C, n2 = measure.corr_mps(st, normalize=False)
             norms.append(n2)
         Cs.append(C)
     return np.array(Cs), np.array(norms)
 
 
-@pytest.mark.parametrize("kind", ["qt", "qsd"])
+@pytest.mark.parametrize("kind", ["qt", "qsd", "qsd_binary"])
 def test_trajectory_average_matches_exact_within_clt(kind):
-    """Sec. 4: the trajectory average reproduces the Lindblad dynamics; error bar eq. (ErrorCLT)."""
+    """Sec. 4: the trajectory average reproduces the Lindblad dynamics; error bar eq. (ErrorCLT).
+    qsd_binary uses the paper's noise eta = +-1 (Sec. 4.2), qsd complex Gaussian increments."""
     L, T, dt, ntraj = 4, 1.0, 0.01, 200
     Cs, norms = _traj_average(kind, ntraj, L, T, dt, seed=11)
     Cex = exact.c_exact(T, [1, 0] * (L // 2))
@@ -303,13 +307,14 @@ def test_trajectory_average_matches_exact_within_clt(kind):
     ne = np.real(np.diag(Cex))
     # 4 sigma plus the O(dt) splitting bias
     assert np.all(np.abs(mean - ne) < 4 * err + 0.02)
-    if kind == "qsd":
+    if kind != "qt":
         # mean norm is conserved (Sec. 4.2)
         assert abs(norms.mean() - 1) < 4 * norms.std(ddof=1) / np.sqrt(ntraj) + 0.02
 
 
 def test_kraus_thin_route_equals_full_diagonalization():
-    """Reading C9: the 2chi_k x 2chi_k route gives the same sum_k A A^+ as diagonalizing R."""
+    """Sec. 3.2, eq. MatrixR / eq. NewPurified with the gamma dt factor: the 2chi_k x 2chi_k Gram
+    route gives the same sum_k A A^+ as diagonalizing the full R."""
     rng = np.random.default_rng(7)
     for dk in (1, 2, 4):
         A = rng.normal(size=(3, 2 * dk, 5)) + 1j * rng.normal(size=(3, 2 * dk, 5))
