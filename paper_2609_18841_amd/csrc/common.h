@@ -103,6 +103,8 @@ struct DevWork {
     double2* qtau;               // items * nmax
     int qr_route;                // 1: wide items (m < n) take the QR route (FP64 mode)
     int jacobi;                  // 1: one-sided Jacobi refinement of the SVD (FP64 mode)
+    double* lsel;                // items * nmax  selected eigenvalues, descending (bisection path)
+    int* fb;                     // items  1: item takes the logged-QL eigenvector path, or null
     double2* Y;                  // items * ysz  Y = Theta~ V, column-major m x r (aliases the Gram slot)
     int ldy;                     // leading dimension of Y (>= mmax)
     size_t ysz;                  // elements per item

@@ -677,6 +677,7 @@ __global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
     const int j = blockIdx.x * QL_TPB + lane;
     ItemDims dm;
     if (!item_dims(s, w, j, dm)) return;
+    if (w.fb && !w.fb[j]) return;  // eigenvectors come from the bisection path
     const int n = w.gsz[j];
     double* gd = w.dd + (size_t)j * w.nmax;
     double* ge = w.ee + (size_t)j * w.nmax;
@@ -779,6 +780,7 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w, int mode) 
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
+    if (w.fb && !w.fb[j]) return;
     const int n = w.gsz[j], tid = threadIdx.x;
     const double* ev = w.dd + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) lamv[i] = ev[i];
@@ -950,65 +952,19 @@ __global__ __launch_bounds__(NT) void k_vecs(DevState s, DevWork w) {
 // Householder back-transformation runs on Z held in registers (4 row groups x 64 columns).
 #define VF_N 128
 #define VF_K 64
+// Back-transformation of the k eigenvectors of T held in LDS (zr, n x k real, row stride zs) by the
+// Householder reflectors: V = Q Z on registers (4 row groups x 64 columns per 256 threads), then
+// V (FP64) and B_{bond+1} = V^+ (storage precision) are written.
 template <class T>
-__global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
-    __shared__ double zr[VF_N * VF_K];
-    __shared__ int lgi[NT];
-    __shared__ double2 lgcs[NT];
-    __shared__ double2 vbuf[VF_N];
-    __shared__ double2 part[NT];
-    ItemDims d;
-    const int j = blockIdx.x;
-    if (!item_dims(s, w, j, d)) return;
-    const int n = w.gsz[j], tid = threadIdx.x;
-    const int k = w.kout[j];
-    const int* sel = w.sel + (size_t)j * w.nmax;
-    for (int e = tid; e < n * k; e += NT) zr[e] = (e / k == sel[e % k]) ? 1.0 : 0.0;
-    __syncthreads();
-    {
-        // Replay, newest rotation first; lane c of wave 0 owns column c.  A chase touches rows
-        // (i, i+1), (i+1, i+2), ...: the row shared by consecutive rotations stays in a register.
-        const int nr = w.nrot[j];
-        const int* li = w.logi + (size_t)j * w.logcap;
-        const double2* lcs = w.logcs + (size_t)j * w.logcap;
-        double xr = 0.0;
-        int ci = -1;
-        for (int hi = nr; hi > 0; hi -= NT) {
-            const int lo = hi - NT > 0 ? hi - NT : 0;
-            const int cnt = hi - lo;
-            if (tid < cnt) {
-                lgi[tid] = li[lo + tid];
-                lgcs[tid] = lcs[lo + tid];
-            }
-            __syncthreads();
-            if (tid < k) {
-                for (int q = cnt - 1; q >= 0; --q) {
-                    const int i = lgi[q];
-                    const double cs = lgcs[q].x, sn = lgcs[q].y;
-                    double x;
-                    if (ci == i) {
-                        x = xr;
-                    } else {
-                        if (ci >= 0) zr[ci * k + tid] = xr;
-                        x = zr[i * k + tid];
-                    }
-                    const double y = zr[(i + 1) * k + tid];
-                    zr[i * k + tid] = cs * x + sn * y;
-                    xr = -sn * x + cs * y;
-                    ci = i + 1;
-                }
-            }
-            __syncthreads();
-        }
-        if (tid < k && ci >= 0) zr[ci * k + tid] = xr;
-    }
-    __syncthreads();
+__device__ __forceinline__ void vf_backtransform(const DevState& s, const DevWork& w, const ItemDims& d, int j, int n,
+                                                 int k, const double* zr, int zs, double2* vbuf, double2* part) {
+    const int tid = threadIdx.x;
     const int g = tid >> 6, col = tid & 63;
     double2 z[VF_N / 4];
 #pragma unroll
     for (int t = 0; t < VF_N / 4; ++t) {
         const int r = g + 4 * t;
-        z[t] = (col < k && r < n) ? mk(zr[r * k + col], 0.0) : mk(0.0, 0.0);
+        z[t] = (col < k && r < n) ? mk(zr[r * zs + col], 0.0) : mk(0.0, 0.0);
     }
     const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
     const double2* tau = w.tau + (size_t)j * w.nmax;
@@ -1053,6 +1009,283 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
             }
         }
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
+    __shared__ double zr[VF_N * VF_K];
+    __shared__ int lgi[NT];
+    __shared__ double2 lgcs[NT];
+    __shared__ double2 vbuf[VF_N];
+    __shared__ double2 part[NT];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    if (w.fb && !w.fb[j]) return;
+    const int n = w.gsz[j], tid = threadIdx.x;
+    const int k = w.kout[j];
+    const int* sel = w.sel + (size_t)j * w.nmax;
+    for (int e = tid; e < n * k; e += NT) zr[e] = (e / k == sel[e % k]) ? 1.0 : 0.0;
+    __syncthreads();
+    {
+        // Replay, newest rotation first; lane c of wave 0 owns column c.  A chase touches rows
+        // (i, i+1), (i+1, i+2), ...: the row shared by consecutive rotations stays in a register.
+        const int nr = w.nrot[j];
+        const int* li = w.logi + (size_t)j * w.logcap;
+        const double2* lcs = w.logcs + (size_t)j * w.logcap;
+        double xr = 0.0;
+        int ci = -1;
+        for (int hi = nr; hi > 0; hi -= NT) {
+            const int lo = hi - NT > 0 ? hi - NT : 0;
+            const int cnt = hi - lo;
+            if (tid < cnt) {
+                lgi[tid] = li[lo + tid];
+                lgcs[tid] = lcs[lo + tid];
+            }
+            __syncthreads();
+            if (tid < k) {
+                for (int q = cnt - 1; q >= 0; --q) {
+                    const int i = lgi[q];
+                    const double cs = lgcs[q].x, sn = lgcs[q].y;
+                    double x;
+                    if (ci == i) {
+                        x = xr;
+                    } else {
+                        if (ci >= 0) zr[ci * k + tid] = xr;
+                        x = zr[i * k + tid];
+                    }
+                    const double y = zr[(i + 1) * k + tid];
+                    zr[i * k + tid] = cs * x + sn * y;
+                    xr = -sn * x + cs * y;
+                    ci = i + 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid < k && ci >= 0) zr[ci * k + tid] = xr;
+    }
+    __syncthreads();
+    vf_backtransform<T>(s, w, d, j, n, k, zr, k, vbuf, part);
+}
+
+// ------------------------------------------------------------------ bisection + twisted factorization (split mode)
+// For n <= 128 and chi <= 64 the split path takes the eigenvalues and the k wanted eigenvectors
+// of T without a rotation log:
+//   k_bisect  lane q of one wavefront finds the q-th largest eigenvalue by bisection on Sturm
+//             counts (every lane runs the same recurrence: no divergence); the count above the
+//             cutoff, the trace (= sum of all eigenvalues) and the kept sum give k, s, the
+//             discarded weight and Lambda as in k_select;
+//   k_tvecs   each wanted eigenvector from the twisted factorization of T - lambda I
+//             (stationary and progressive LDL^T sweeps, twist where |gamma_r| is smallest), one
+//             modified Gram-Schmidt pass in descending order, then the Householder
+//             back-transformation.
+// Eigenvectors of eigenvalues closer than 1e-11 lambda_max (a degenerate multiplet), or a
+// factorization that overflows, send the item to the logged QL path (k_steqr, k_select,
+// k_vecs_fast run on those items only).
+#define BS_MAXIT 64
+#define TV_TIGHT 1e-11
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+// number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots of T - x I)
+__device__ __forceinline__ int sturm_count(const double* sd, const double* se2, int n, double x, double pivmin) {
+    double q = sd[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0 ? 1 : 0;
+    for (int i = 1; i < n; ++i) {
+        q = (sd[i] - x) - se2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0 ? 1 : 0;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(64) void k_bisect(DevState s, DevWork w) {
+    __shared__ double sd[VF_N], se2[VF_N];
+    const int j = blockIdx.x, lane = threadIdx.x;
+    if (j >= w.nitems) return;
+    ItemDims dm;
+    if (!item_dims(s, w, j, dm)) {
+        if (lane == 0) w.fb[j] = 0;
+        return;
+    }
+    const int n = w.gsz[j];
+    const double* gd = w.dd + (size_t)j * w.nmax;
+    const double* ge = w.ee + (size_t)j * w.nmax;
+    double glo = 1e300, ghi = -1e300, tr = 0.0, emax2 = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double di = gd[i];
+        const double el = i > 0 ? fabs(ge[i - 1]) : 0.0, er = i + 1 < n ? fabs(ge[i]) : 0.0;
+        const double e2 = i + 1 < n ? ge[i] * ge[i] : 0.0;
+        sd[i] = di;
+        se2[i] = e2;
+        glo = fmin(glo, di - el - er);
+        ghi = fmax(ghi, di + el + er);
+        tr += di;
+        emax2 = fmax(emax2, e2);
+    }
+    glo = wave_min(glo);
+    ghi = wave_max(ghi);
+    tr = wave_sum(tr);
+    emax2 = wave_max(emax2);
+    __syncthreads();
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    const double tol = 4.0 * DBL_EPSILON * tnorm + 2.0 * pivmin;
+    const int t = n - 1 - (lane < n ? lane : n - 1);  // ascending index of this lane's eigenvalue
+    double lo = glo - tol, hi = ghi + tol;
+    for (int it = 0; it < BS_MAXIT; ++it) {
+        if (__all(hi - lo <= tol)) break;
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_count(sd, se2, n, mid, pivmin) <= t) lo = mid;
+        else hi = mid;
+    }
+    const double lam = 0.5 * (lo + hi);
+    const double lmax = __shfl(lam, 0);
+    int cnt = n;
+    if (!(s.cutoff2 < 1e-14)) cnt = n - sturm_count(sd, se2, n, s.cutoff2 * lmax, pivmin);
+    int k = cnt < s.chi ? cnt : s.chi;
+    k = k < dm.m ? k : dm.m;
+    k = k < n ? k : n;
+    k = k < VF_K ? k : VF_K;
+    if (k < 1) k = 1;
+    const double kept = wave_sum(lane < k ? lam : 0.0);
+    const double sv = kept > 0.0 ? sqrt(kept) : 1.0;
+    const double nxt = __shfl_down(lam, 1);
+    const bool tight = lane + 1 < k && !(lam - nxt > TV_TIGHT * lmax);
+    const bool bad = !(lmax > 0.0) || !(kept == kept) || !(tr == tr);
+    const int fall = (__any(tight) || bad) ? 1 : 0;
+    if (lane < k) {
+        lam_ptr(s, dm.b, dm.bond)[lane] = lam > 0.0 ? sqrt(lam) / sv : 0.0;
+        w.lsel[(size_t)j * w.nmax + lane] = lam;
+    }
+    if (lane == 0) {
+        const double wgt = tr > 0.0 ? (tr - kept) / tr : 0.0;
+        w.kout[j] = k;
+        w.sout[j] = sv;
+        w.wout[j] = wgt > 0.0 ? wgt : 0.0;
+        w.fb[j] = fall;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
+    __shared__ double zr[VF_N * VF_K];
+    __shared__ double sd[VF_N], se[VF_N];
+    __shared__ double2 vbuf[VF_N];
+    __shared__ double2 part[NT];
+    __shared__ int bad;
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    if (w.fb[j]) return;
+    const int n = w.gsz[j], tid = threadIdx.x, k = w.kout[j];
+    const double* gd = w.dd + (size_t)j * w.nmax;
+    const double* ge = w.ee + (size_t)j * w.nmax;
+    for (int i = tid; i < n; i += NT) {
+        sd[i] = gd[i];
+        se[i] = i + 1 < n ? ge[i] : 0.0;
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    double emax2 = 0.0;
+    for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, se[i] * se[i]);
+    const double pivmin = DBL_MIN * fmax(1.0, emax2);
+    // column c = 16 * wave + lane (lanes 0..15 of each wavefront): four independent recurrences per CU SIMD
+    const int wv = tid >> 6, ln = tid & 63, c = 16 * wv + ln;
+    if (ln < 16 && c < k) {
+        const double lam = w.lsel[(size_t)j * w.nmax + c];
+        // progressive (bottom-up) pivots D-_i of T - lam I, stored in the column
+        double dm = sd[n - 1] - lam;
+        if (fabs(dm) < pivmin) dm = -pivmin;
+        zr[(n - 1) * VF_K + c] = dm;
+        for (int i = n - 2; i >= 0; --i) {
+            dm = (sd[i] - lam) - se[i] * se[i] / dm;
+            if (fabs(dm) < pivmin) dm = -pivmin;
+            zr[i * VF_K + c] = dm;
+        }
+        // stationary (top-down) pivots D+_i; twist index r = argmin |gamma_i|, gamma_i = D+_i + D-_i - (d_i - lam)
+        double dp = sd[0] - lam;
+        if (fabs(dp) < pivmin) dp = -pivmin;
+        int r = 0;
+        double gbest = fabs(zr[c]);
+        for (int i = 1; i < n; ++i) {
+            dp = (sd[i] - lam) - se[i - 1] * se[i - 1] / dp;
+            if (fabs(dp) < pivmin) dp = -pivmin;
+            const double gam = fabs(dp + zr[i * VF_K + c] - (sd[i] - lam));
+            if (gam < gbest) {
+                gbest = gam;
+                r = i;
+            }
+        }
+        // D+_i for i < r replace D-_i there (D-_i is needed only below the twist)
+        dp = sd[0] - lam;
+        if (fabs(dp) < pivmin) dp = -pivmin;
+        for (int i = 0; i < r; ++i) {
+            if (i > 0) {
+                dp = (sd[i] - lam) - se[i - 1] * se[i - 1] / dp;
+                if (fabs(dp) < pivmin) dp = -pivmin;
+            }
+            zr[i * VF_K + c] = dp;
+        }
+        // z_r = 1; below: z_{i+1} = -(e_i / D-_{i+1}) z_i; above: z_i = -(e_i / D+_i) z_{i+1}
+        double zi = 1.0, nrm = 1.0;
+        zr[r * VF_K + c] = 1.0;
+        for (int i = r; i + 1 < n; ++i) {
+            zi = -(se[i] / zr[(i + 1) * VF_K + c]) * zi;
+            zr[(i + 1) * VF_K + c] = zi;
+            nrm += zi * zi;
+        }
+        zi = 1.0;
+        for (int i = r - 1; i >= 0; --i) {
+            zi = -(se[i] / zr[i * VF_K + c]) * zi;
+            zr[i * VF_K + c] = zi;
+            nrm += zi * zi;
+        }
+        if (!(nrm < 1e300)) bad = 1;
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < n; ++i) zr[i * VF_K + c] *= inv;
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) w.fb[j] = 1;
+        return;
+    }
+    // modified Gram-Schmidt in descending eigenvalue order: column p is final, then removed from p+1..k-1
+    const int g = tid >> 6, col = tid & 63;
+    for (int p = 0; p + 1 < k; ++p) {
+        double acc = 0.0;
+        if (col > p && col < k)
+            for (int i = g; i < n; i += 4) acc += zr[i * VF_K + p] * zr[i * VF_K + col];
+        part[tid].x = acc;
+        __syncthreads();
+        const double dot = part[col].x + part[64 + col].x + part[128 + col].x + part[192 + col].x;
+        double sq = 0.0;
+        if (col > p && col < k)
+            for (int i = g; i < n; i += 4) {
+                const double v = zr[i * VF_K + col] - dot * zr[i * VF_K + p];
+                zr[i * VF_K + col] = v;
+                sq += v * v;
+            }
+        __syncthreads();
+        part[tid].x = sq;
+        __syncthreads();
+        if (col > p && col < k) {
+            const double inv = 1.0 / sqrt(part[col].x + part[64 + col].x + part[128 + col].x + part[192 + col].x);
+            for (int i = g; i < n; i += 4) zr[i * VF_K + col] *= inv;
+        }
+        __syncthreads();
+    }
+    vf_backtransform<T>(s, w, d, j, n, k, zr, VF_K, vbuf, part);
 }
 
 // ------------------------------------------------------------------ Hastings split
@@ -1295,6 +1528,23 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
     else
         hipLaunchKernelGGL(k_hetrd<false>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_HETRD, st);
+    if (w.fb) {
+        // split mode, n <= 128, chi <= 64: bisection + twisted factorization; the logged QL path
+        // runs only on the items that k_bisect or k_tvecs hand over
+        prof_begin(prof, TN_K_STEQR, st);
+        hipLaunchKernelGGL(k_bisect, dim3(w.nitems), dim3(64), 0, st, s, w);
+        prof_end(prof, TN_K_STEQR, st);
+        prof_begin(prof, TN_K_VECS, st);
+        hipLaunchKernelGGL(k_tvecs<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        prof_end(prof, TN_K_VECS, st);
+        hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+        hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 0);
+        hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        prof_begin(prof, TN_K_SPLIT, st);
+        hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+        prof_end(prof, TN_K_SPLIT, st);
+        return;
+    }
     prof_begin(prof, TN_K_STEQR, st);
     if (w.nmax <= QL_LDS_N)
         hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);

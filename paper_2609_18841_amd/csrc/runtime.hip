@@ -67,7 +67,7 @@ struct Layout {
     size_t ws_bytes, total;
     // workspace sub-layout (update)
     size_t u_theta, u_gram, u_refl, u_tau, u_dd, u_ee, u_logi, u_logcs, u_nrot, u_sel, u_kout, u_sout, u_wout, u_V,
-        u_z, u_p, u_gsz, u_qra, u_qtau, u_bytes;
+        u_z, u_p, u_gsz, u_qra, u_qtau, u_lsel, u_fb, u_bytes;
     // workspace sub-layout (measurement)
     size_t m_R, m_E, m_X, m_Y, m_W, m_bytes;
 };
@@ -151,6 +151,8 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.u_gsz = u; u = al(u + (size_t)chunk * 4);
     ly.u_qra = u; if (prec == 0) u = al(u + (size_t)chunk * nmax * nmax * 16);
     ly.u_qtau = u; if (prec == 0) u = al(u + (size_t)chunk * nmax * 16);
+    ly.u_lsel = u; u = al(u + (size_t)chunk * nmax * 8);
+    ly.u_fb = u; u = al(u + (size_t)chunk * 4);
     ly.u_bytes = u;
     // measurement workspace
     size_t m = 0;
@@ -595,6 +597,9 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
         w.Y = w.gram;  // the Gram slot is free once the Householder reduction has read it
         w.ldy = s->nmax;
         w.ysz = (size_t)s->nmax * s->nmax;
+        w.lsel = reinterpret_cast<double*>(ws + s->lay.u_lsel);
+        // split mode with n <= 128 and chi <= 64 takes the bisection path (kernels in k_update.hip)
+        w.fb = (s->prec == 1 && s->nmax <= 128 && s->chi <= 64) ? reinterpret_cast<int*>(ws + s->lay.u_fb) : nullptr;
         launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
         HIPCHK(hipGetLastError());
     }
