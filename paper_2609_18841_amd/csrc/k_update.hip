@@ -395,152 +395,75 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
     }
 }
 
-// Register-resident variant for n <= 128 (512 threads): the full Hermitian matrix is kept in
-// registers, thread t owning row r = t/4 and the 32 columns of block t%4.  Column i of the
-// trailing matrix is read as the conjugate of row i (Hermitian), so no dynamic register
-// indexing is needed; the matrix-vector product reduces over the 4 threads of a row.
+// Register-resident reduction for n <= 128 (512 threads, one item per workgroup).  Wave
+// (rh, cb) holds rows rh*64 + lane and the 32 columns of block cb, so whole waves drop out once
+// their rows or columns are reduced (work ~ n^3/3).  Two block barriers per step:
+//   (B) after the partial products A v of every column block (and the owner of row i+1 has
+//       published that row as it was before this step's update);
+//   (C) after p = tau A v and p^+ v are final.
+// After (C) every wave updates its tile and, redundantly, the row i+1 it will need next, so it
+// forms the next reflector itself into a wave-private copy of v: no wave waits for a serial
+// reflector step.  Reflector conventions follow LAPACK zhetd2 (lower): H_i = I - tau v v^+,
+// v[i+1] = 1, beta real, so T is real symmetric tridiagonal.
 #define HR_N 128
 #define HR_NT 512
-__device__ __forceinline__ double quad_sum(double v) {
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    return v;
-}
-__global__ __launch_bounds__(HR_NT) void k_hetrd_reg(DevState s, DevWork w) {
-    __shared__ double2 rowbuf[HR_N], vv[HR_N], ww[HR_N];
-    __shared__ double redd[HR_NT / 64];
-    __shared__ double2 redc[HR_NT / 64];
-    __shared__ double2 sh_tau, sh_alpha2;
-    ItemDims d;
-    const int j = blockIdx.x;
-    if (!item_dims(s, w, j, d)) return;
-    const int n = w.gsz[j], tid = threadIdx.x;
-    const int r = tid >> 2, cb = tid & 3, c0 = cb * 32;
-    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
-    double* dd = w.dd + (size_t)j * w.nmax;
-    double* ee = w.ee + (size_t)j * w.nmax;
-    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
-    double2* tau = w.tau + (size_t)j * w.nmax;
-    // the Gram kernel wrote the lower triangle (and the diagonal blocks); rebuild the full row
-    double2 a[32];
-#pragma unroll
-    for (int t = 0; t < 32; ++t) {
-        const int c = c0 + t;
-        double2 v = mk(0.0, 0.0);
-        if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
-        a[t] = v;
+#define HR_NW (HR_NT / 64)
+
+// Reflector of the (updated) row i, given as two entries per lane (columns lane, lane + 64):
+// writes v into this wave's private vector and returns tau; when wr, also stores d_i, e_i,
+// tau_i and v (into reflrow, the reflector's row of the reflector table).
+__device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 x0, double2 x1, double2* vp,
+                                                bool wr, double* dd, double* ee, double2* tau, double2* reflrow) {
+    const int c0 = lane, c1 = lane + 64;
+    double p = 0.0;
+    if (c0 >= i + 2 && c0 < n) p += x0.x * x0.x + x0.y * x0.y;
+    if (c1 >= i + 2 && c1 < n) p += x1.x * x1.x + x1.y * x1.y;
+    p = wave_sum(p);
+    // alpha = conj(row[i+1]) and d_i = row[i] from the lanes that hold them
+    const int la = (i + 1) & 63, ld = i & 63;
+    const double2 xa = (i + 1) < 64 ? x0 : x1, xd = i < 64 ? x0 : x1;
+    const double2 alpha = mk(readlane_f64(xa.x, la), -readlane_f64(xa.y, la));
+    const double di = readlane_f64(xd.x, ld);
+    double2 tv, sc;
+    double beta;
+    if (p == 0.0 && alpha.y == 0.0) {
+        tv = mk(0.0, 0.0);
+        beta = alpha.x;
+        sc = mk(1.0, 0.0);
+    } else {
+        const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
+        beta = alpha.x >= 0.0 ? -nrm : nrm;
+        tv = mk((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 z = mk(alpha.x - beta, alpha.y);
+        const double den = z.x * z.x + z.y * z.y;
+        sc = mk(z.x / den, -z.y / den);
     }
-    for (int i = 0; i + 1 < n; ++i) {
-        // row i of the current matrix -> LDS (its conjugate is column i)
-        if (r == i) {
-#pragma unroll
-            for (int t = 0; t < 32; ++t) rowbuf[c0 + t] = a[t];
+    const double2 v0 = (c0 > i && c0 < n) ? ((c0 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x0), sc)) : mk(0.0, 0.0);
+    const double2 v1 = (c1 > i && c1 < n) ? ((c1 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x1), sc)) : mk(0.0, 0.0);
+    vp[c0] = v0;
+    vp[c1] = v1;
+    if (wr) {
+        if (c0 > i && c0 < n) reflrow[c0 - i - 1] = v0;
+        if (c1 > i && c1 < n) reflrow[c1 - i - 1] = v1;
+        if (lane == 0) {
+            dd[i] = di;
+            ee[i] = beta;
+            tau[i] = tv;
         }
-        __syncthreads();
-        if (tid < 64) {
-            // ||x||^2, x = A[i+2.., i] = conj(row i)[i+2..]
-            double p = 0.0;
-            for (int c = i + 2 + tid; c < n; c += 64) {
-                double2 x = rowbuf[c];
-                p += x.x * x.x + x.y * x.y;
-            }
-            p = wave_sum(p);
-            if (tid == 0) {
-                double2 alpha = cconj(rowbuf[i + 1]);
-                double2 t, sc;
-                double beta;
-                if (p == 0.0 && alpha.y == 0.0) {
-                    t = mk(0.0, 0.0);
-                    beta = alpha.x;
-                    sc = mk(1.0, 0.0);
-                } else {
-                    double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
-                    beta = alpha.x >= 0.0 ? -nrm : nrm;
-                    t = mk((beta - alpha.x) / beta, -alpha.y / beta);
-                    double2 z = mk(alpha.x - beta, alpha.y);
-                    double den = z.x * z.x + z.y * z.y;
-                    sc = mk(z.x / den, -z.y / den);
-                }
-                sh_tau = t;
-                dd[i] = rowbuf[i].x;
-                ee[i] = beta;
-                tau[i] = t;
-                sh_alpha2 = sc;  // scale of x, used just below
-            }
-        }
-        __syncthreads();
-        const double2 tv = sh_tau, sc = sh_alpha2;
-        for (int c = i + 1 + tid; c < n; c += HR_NT) {
-            double2 v = (c == i + 1) ? mk(1.0, 0.0) : cmul(cconj(rowbuf[c]), sc);
-            vv[c] = v;
-            refl[(size_t)i * w.nmax + (c - i - 1)] = v;
-        }
-        __syncthreads();
-        if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform
-        // p_r = tau * sum_c A[r][c] v_c over the trailing block
-        double2 acc = mk(0.0, 0.0);
-#pragma unroll
-        for (int t = 0; t < 32; ++t) {
-            const int c = c0 + t;
-            if (c > i && c < n) cfma(acc, a[t], vv[c]);
-        }
-        acc.x = quad_sum(acc.x);
-        acc.y = quad_sum(acc.y);
-        if (cb == 0 && r > i && r < n) ww[r] = cmul(tv, acc);
-        __syncthreads();
-        // alpha2 = -1/2 tau (p^+ v)
-        if (tid < 64) {
-            double2 q = mk(0.0, 0.0);
-            for (int c = i + 1 + tid; c < n; c += 64) cfmac(q, ww[c], vv[c]);
-            q.x = wave_sum(q.x);
-            q.y = wave_sum(q.y);
-            if (tid == 0) {
-                double2 a2 = cmul(tv, q);
-                redc[0] = mk(-0.5 * a2.x, -0.5 * a2.y);
-            }
-        }
-        __syncthreads();
-        const double2 a2 = redc[0];
-        // w = p + alpha2 v  (each thread forms the entries it needs)
-        if (r > i && r < n) {
-            double2 vr = vv[r];
-            double2 wr = ww[r];
-            cfma(wr, a2, vr);
-#pragma unroll
-            for (int t = 0; t < 32; ++t) {
-                const int c = c0 + t;
-                if (c > i && c < n) {
-                    double2 vc = vv[c];
-                    double2 wc = ww[c];
-                    cfma(wc, a2, vc);
-                    double2 u1 = cmulc(wc, vr);  // v_r conj(w_c)
-                    double2 u2 = cmulc(vc, wr);  // w_r conj(v_c)
-                    a[t].x -= u1.x + u2.x;
-                    a[t].y -= u1.y + u2.y;
-                }
-            }
-        }
-        __syncthreads();
     }
-    if (r == n - 1) {
-#pragma unroll
-        for (int t = 0; t < 32; ++t)
-            if (c0 + t == n - 1) {
-                dd[n - 1] = a[t].x;
-                ee[n - 1] = 0.0;
-            }
-    }
+    // the private vector is read by other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return tv;
 }
 
-// Wave-tiled register variant (n <= 128, 512 threads): wave (rh, cb) holds rows rh*64 + lane
-// and the 32 columns of block cb, so whole waves drop out once their rows or columns are
-// reduced (work ~ n^3/3).  Every lane of wave 0 forms the reflector redundantly from a wave
-// reduction (no serial lane), and row sums of the matrix-vector product go through LDS.
 __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
-    __shared__ double2 rowbuf[HR_N], vv[HR_N], ww[HR_N];
+    __shared__ double2 vpriv[HR_NW][HR_N];
+    __shared__ double2 rowold[2][HR_N];
+    __shared__ double2 ww[HR_N];
     __shared__ double2 pbuf[4 * HR_N];
     __shared__ double2 dotp[2];
-    __shared__ double2 sh_tau;
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
@@ -553,6 +476,7 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
     double* ee = w.ee + (size_t)j * w.nmax;
     double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
     double2* tau = w.tau + (size_t)j * w.nmax;
+    double2* vp = vpriv[wv];
     double2 a[32];
 #pragma unroll
     for (int t = 0; t < 32; ++t) {
@@ -561,104 +485,112 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
         if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
         a[t] = v;
     }
-    for (int i = 0; i + 1 < n; ++i) {
-        if (r == i) {
+    if (n == 1) {
+        if (tid == 0) {
+            dd[0] = a[0].x;
+            ee[0] = 0.0;
+        }
+        return;
+    }
+    // reflector 0 from the unreduced row 0
+    if (r == 0) {
 #pragma unroll
-            for (int t = 0; t < 32; ++t) rowbuf[c0 + t] = a[t];
-        }
-        __syncthreads();
-        if (wv == 0) {
-            double p = 0.0;
-            for (int c = i + 2 + lane; c < n; c += 64) {
-                double2 x = rowbuf[c];
-                p += x.x * x.x + x.y * x.y;
-            }
-            p = wave_sum(p);
-            const double2 alpha = cconj(rowbuf[i + 1]);
-            double2 tv, sc;
-            double beta;
-            if (p == 0.0 && alpha.y == 0.0) {
-                tv = mk(0.0, 0.0);
-                beta = alpha.x;
-                sc = mk(1.0, 0.0);
-            } else {
-                double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
-                beta = alpha.x >= 0.0 ? -nrm : nrm;
-                tv = mk((beta - alpha.x) / beta, -alpha.y / beta);
-                double2 z = mk(alpha.x - beta, alpha.y);
-                double den = z.x * z.x + z.y * z.y;
-                sc = mk(z.x / den, -z.y / den);
-            }
-            // vv is zero outside (i, n): the trailing-block loops below need no predicates
-            for (int c = lane; c < HR_N; c += 64) {
-                double2 v = mk(0.0, 0.0);
-                if (c > i && c < n) {
-                    v = (c == i + 1) ? mk(1.0, 0.0) : cmul(cconj(rowbuf[c]), sc);
-                    refl[(size_t)i * w.nmax + (c - i - 1)] = v;
-                }
-                vv[c] = v;
-            }
-            if (lane == 0) {
-                sh_tau = tv;
-                dd[i] = rowbuf[i].x;
-                ee[i] = beta;
-                tau[i] = tv;
-            }
-        }
-        __syncthreads();
-        const double2 tv = sh_tau;
-        if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform
+        for (int t = 0; t < 32; ++t) rowold[0][c0 + t] = a[t];
+    }
+    __syncthreads();
+    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vp, wv == 0, dd, ee, tau,
+                              refl);
+    for (int i = 0; i + 1 < n; ++i) {
+        const int buf = (i + 1) & 1;
+        const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
         const bool rows_live = (rh * 64 + 63 > i) && (rh * 64 < n);
         const bool cols_live = (c0 + 31 > i) && (c0 < n);
-        // partial p_r over this column block
-        double2 acc = mk(0.0, 0.0);
-        if (rows_live && cols_live) {
+        // partial p_r over this column block; the owner publishes row i+1 before the update
+        if (act) {
+            double2 acc = mk(0.0, 0.0);
+            if (rows_live && cols_live) {
 #pragma unroll
-            for (int t = 0; t < 32; ++t) cfma(acc, a[t], vv[c0 + t]);
+                for (int t = 0; t < 32; ++t) cfma(acc, a[t], vp[c0 + t]);
+            }
+            pbuf[cb * HR_N + r] = acc;
         }
-        pbuf[cb * HR_N + r] = acc;
-        __syncthreads();
-        // finalize p = tau A v for the rows of this half, and the half's part of p^+ v
-        if (cb == 0) {
+        if (r == i + 1) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) rowold[buf][c0 + t] = a[t];
+        }
+        __syncthreads();  // (B)
+        if (act && cb == 0) {
             double2 q = mk(0.0, 0.0);
             double2 pr = mk(0.0, 0.0);
             if (r > i && r < n) {
                 pr = cadd(cadd(pbuf[r], pbuf[HR_N + r]), cadd(pbuf[2 * HR_N + r], pbuf[3 * HR_N + r]));
                 pr = cmul(tv, pr);
-                cfmac(q, pr, vv[r]);
+                cfmac(q, pr, vp[r]);
             }
             ww[r] = pr;  // zero outside (i, n)
             q.x = wave_sum(q.x);
             q.y = wave_sum(q.y);
             if (lane == 0) dotp[rh] = q;
         }
-        __syncthreads();
-        const double2 a2t = cmul(tv, cadd(dotp[0], dotp[1]));
-        const double2 a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
-        if (rows_live && cols_live && r > i && r < n) {
-            const double2 vr = vv[r];
-            double2 wr = ww[r];
-            cfma(wr, a2, vr);
-            // -conj(v_r), -conj(w_r): a[t] -= v_r conj(w_c) + w_r conj(v_c)  ==  conj(conj(...))
+        __syncthreads();  // (C)
+        double2 a2 = mk(0.0, 0.0);
+        if (act) {
+            const double2 a2t = cmul(tv, cadd(dotp[0], dotp[1]));
+            a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
+            if (rows_live && cols_live && r > i && r < n) {
+                const double2 vr = vp[r];
+                double2 wr = ww[r];
+                cfma(wr, a2, vr);
+                // a[t] -= v_r conj(w_c) + w_r conj(v_c)
 #pragma unroll
-            for (int t = 0; t < 32; ++t) {
-                const double2 vc = vv[c0 + t];
-                double2 wc = ww[c0 + t];
-                cfma(wc, a2, vc);
-                double2 u1 = cmulc(wc, vr);
-                double2 u2 = cmulc(vc, wr);
-                a[t].x -= u1.x + u2.x;
-                a[t].y -= u1.y + u2.y;
+                for (int t = 0; t < 32; ++t) {
+                    const double2 vc = vp[c0 + t];
+                    double2 wc = ww[c0 + t];
+                    cfma(wc, a2, vc);
+                    const double2 u1 = cmulc(wc, vr);
+                    const double2 u2 = cmulc(vc, wr);
+                    a[t].x -= u1.x + u2.x;
+                    a[t].y -= u1.y + u2.y;
+                }
             }
         }
-    }
-    if (r == n - 1) {
+        // row i+1 after this update (the same arithmetic as the owner's), then reflector i+1
+        double2 x0 = rowold[buf][lane], x1 = rowold[buf][lane + 64];
+        if (act) {
+            const int rn = i + 1;
+            const double2 vr = vp[rn];
+            double2 wr = ww[rn];
+            cfma(wr, a2, vr);
 #pragma unroll
-        for (int t = 0; t < 32; ++t)
-            if (c0 + t == n - 1) {
-                dd[n - 1] = a[t].x;
+            for (int h = 0; h < 2; ++h) {
+                const int c = lane + 64 * h;
+                if (c > i && c < n) {
+                    const double2 vc = vp[c];
+                    double2 wc = ww[c];
+                    cfma(wc, a2, vc);
+                    const double2 u1 = cmulc(wc, vr);
+                    const double2 u2 = cmulc(vc, wr);
+                    double2& x = h == 0 ? x0 : x1;
+                    x.x -= u1.x + u2.x;
+                    x.y -= u1.y + u2.y;
+                }
+            }
+        }
+        // every lane has read v_i (vp) above before the reflector overwrites it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (i + 2 < n) {
+            tv = hr_reflector(i + 1, n, lane, x0, x1, vp, wv == 0, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
+        } else if (wv == 0) {
+            // last diagonal entry
+            const double2 xd = (n - 1) < 64 ? x0 : x1;
+            const double dl = readlane_f64(xd.x, (n - 1) & 63);
+            if (lane == 0) {
+                dd[n - 1] = dl;
                 ee[n - 1] = 0.0;
             }
+        }
     }
 }
 
@@ -677,7 +609,7 @@ __global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
     const int j = blockIdx.x * QL_TPB + lane;
     ItemDims dm;
     if (!item_dims(s, w, j, dm)) return;
-    if (w.fb && !w.fb[j]) return;  // eigenvectors come from the bisection path
+    if (w.fb && w.fb[j] != 1) return;  // eigenvectors come from the bisection path
     const int n = w.gsz[j];
     double* gd = w.dd + (size_t)j * w.nmax;
     double* ge = w.ee + (size_t)j * w.nmax;
@@ -780,7 +712,7 @@ __global__ __launch_bounds__(NT) void k_select(DevState s, DevWork w, int mode) 
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    if (w.fb && !w.fb[j]) return;
+    if (w.fb && w.fb[j] != 1) return;
     const int n = w.gsz[j], tid = threadIdx.x;
     const double* ev = w.dd + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) lamv[i] = ev[i];
@@ -968,12 +900,20 @@ __device__ __forceinline__ void vf_backtransform(const DevState& s, const DevWor
     }
     const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
     const double2* tau = w.tau + (size_t)j * w.nmax;
+    // reflector rows stream from memory one step ahead of their use: row i is in registers
+    // (cur) while row i+1 is applied, so the global-memory latency overlaps the arithmetic
+    double2 cur = (n >= 2 && tid < 1) ? refl[(size_t)(n - 2) * w.nmax + tid] : mk(0.0, 0.0);
+    double2 tv_cur = n >= 2 ? tau[n - 2] : mk(0.0, 0.0);
     for (int i = n - 2; i >= 0; --i) {
         const int len = n - 1 - i;
-        const double2 tv = tau[i];
+        const double2 tv = tv_cur;
+        __syncthreads();  // the previous reflector is no longer read from vbuf / part
+        if (tid < len) vbuf[tid] = cur;
+        if (i > 0) {
+            cur = tid < len + 1 ? refl[(size_t)(i - 1) * w.nmax + tid] : mk(0.0, 0.0);
+            tv_cur = tau[i - 1];
+        }
         if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform across the block
-        __syncthreads();
-        for (int r = tid; r < len; r += NT) vbuf[r] = refl[(size_t)i * w.nmax + r];
         __syncthreads();
         double2 acc = mk(0.0, 0.0);
 #pragma unroll
@@ -1021,7 +961,7 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    if (w.fb && !w.fb[j]) return;
+    if (w.fb && w.fb[j] != 1) return;
     const int n = w.gsz[j], tid = threadIdx.x;
     const int k = w.kout[j];
     const int* sel = w.sel + (size_t)j * w.nmax;
@@ -1081,9 +1021,12 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
 //             back-transformation.
 // Eigenvectors of eigenvalues closer than 1e-11 lambda_max (a degenerate multiplet), or a
 // factorization that overflows, send the item to the logged QL path (k_steqr, k_select,
-// k_vecs_fast run on those items only).
+// k_vecs_fast run on those items only): fb = 1.  Computed eigenvectors are orthogonal to about
+// eps lambda_max / gap, so the Gram-Schmidt pass runs only when some kept gap is below
+// 1e-6 lambda_max (fb = 2); otherwise fb = 0.
 #define BS_MAXIT 64
 #define TV_TIGHT 1e-11
+#define TV_SEP 1e-6
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -1162,8 +1105,9 @@ __global__ __launch_bounds__(64) void k_bisect(DevState s, DevWork w) {
     const double sv = kept > 0.0 ? sqrt(kept) : 1.0;
     const double nxt = __shfl_down(lam, 1);
     const bool tight = lane + 1 < k && !(lam - nxt > TV_TIGHT * lmax);
+    const bool close = lane + 1 < k && !(lam - nxt > TV_SEP * lmax);
     const bool bad = !(lmax > 0.0) || !(kept == kept) || !(tr == tr);
-    const int fall = (__any(tight) || bad) ? 1 : 0;
+    const int fall = (__any(tight) || bad) ? 1 : (__any(close) ? 2 : 0);
     if (lane < k) {
         lam_ptr(s, dm.b, dm.bond)[lane] = lam > 0.0 ? sqrt(lam) / sv : 0.0;
         w.lsel[(size_t)j * w.nmax + lane] = lam;
@@ -1187,8 +1131,9 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    if (w.fb[j]) return;
+    if (w.fb[j] == 1) return;
     const int n = w.gsz[j], tid = threadIdx.x, k = w.kout[j];
+    const bool mgs = w.fb[j] == 2;
     const double* gd = w.dd + (size_t)j * w.nmax;
     const double* ge = w.ee + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) {
@@ -1262,7 +1207,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
     }
     // modified Gram-Schmidt in descending eigenvalue order: column p is final, then removed from p+1..k-1
     const int g = tid >> 6, col = tid & 63;
-    for (int p = 0; p + 1 < k; ++p) {
+    for (int p = 0; mgs && p + 1 < k; ++p) {
         double acc = 0.0;
         if (col > p && col < k)
             for (int i = g; i < n; i += 4) acc += zr[i * VF_K + p] * zr[i * VF_K + col];
