@@ -397,20 +397,47 @@ __global__ __launch_bounds__(NT) void k_hetrd(DevState s, DevWork w) {
 
 // Register-resident reduction for n <= 128 (512 threads, one item per workgroup).  Wave
 // (rh, cb) holds rows rh*64 + lane and the 32 columns of block cb, so whole waves drop out once
-// their rows or columns are reduced (work ~ n^3/3).  Two block barriers per step:
-//   (B) after the partial products A v of every column block (and the owner of row i+1 has
-//       published that row as it was before this step's update);
-//   (C) after p = tau A v and p^+ v are final.
-// After (C) every wave updates its tile and, redundantly, the row i+1 it will need next, so it
-// forms the next reflector itself into a wave-private copy of v: no wave waits for a serial
-// reflector step.  Reflector conventions follow LAPACK zhetd2 (lower): H_i = I - tau v v^+,
-// v[i+1] = 1, beta real, so T is real symmetric tridiagonal.
+// their rows or columns are reduced (work ~ n^3/3).  Step i has two block barriers:
+//   (B) the partial products A v_i of every column block are in LDS, and the owner of row i+1
+//       has published that row as it was before update i;
+//   (C) p = tau A v_i and p^+ v_i are final.
+// After (C) every wave forms the updated row i+1 and from it the next reflector v_{i+1} (into
+// a wave-private, step-parity double-buffered vector), then makes one pass over its tile that
+// applies update i and accumulates A v_{i+1} for the next step.  Reflector conventions follow
+// LAPACK zhetd2 (lower): H_i = I - tau v v^+, v[i+1] = 1, beta real, so T is real symmetric
+// tridiagonal.
 #define HR_N 128
 #define HR_NT 512
 #define HR_NW (HR_NT / 64)
+#define HR_CW 32                 // columns per wave tile
+#define HR_NCB (HR_N / HR_CW)    // column blocks
+
+// x from lane src - that lane's value where the DPP control selects one, 0 in rows masked off
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// sum over the 64 lanes through DPP lane moves (no LDS round trips); every lane gets the total
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_f64<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);  // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);  // row_bcast15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);  // row_bcast31 into rows 2 and 3
+    return readlane_f64(v, 63);
+}
+
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Reflector of the (updated) row i, given as two entries per lane (columns lane, lane + 64):
-// writes v into this wave's private vector and returns tau; when wr, also stores d_i, e_i,
+// writes v into this wave's private vector vp and returns tau; when wr, also stores d_i, e_i,
 // tau_i and v (into reflrow, the reflector's row of the reflector table).
 __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 x0, double2 x1, double2* vp,
                                                 bool wr, double* dd, double* ee, double2* tau, double2* reflrow) {
@@ -418,7 +445,7 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
     double p = 0.0;
     if (c0 >= i + 2 && c0 < n) p += x0.x * x0.x + x0.y * x0.y;
     if (c1 >= i + 2 && c1 < n) p += x1.x * x1.x + x1.y * x1.y;
-    p = wave_sum(p);
+    p = wave_sum_dpp(p);
     // alpha = conj(row[i+1]) and d_i = row[i] from the lanes that hold them
     const int la = (i + 1) & 63, ld = i & 63;
     const double2 xa = (i + 1) < 64 ? x0 : x1, xd = i < 64 ? x0 : x1;
@@ -440,6 +467,7 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
     }
     const double2 v0 = (c0 > i && c0 < n) ? ((c0 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x0), sc)) : mk(0.0, 0.0);
     const double2 v1 = (c1 > i && c1 < n) ? ((c1 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x1), sc)) : mk(0.0, 0.0);
+    wave_fence();  // earlier reads of this buffer by other lanes are done
     vp[c0] = v0;
     vp[c1] = v1;
     if (wr) {
@@ -451,35 +479,43 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
             tau[i] = tv;
         }
     }
-    // the private vector is read by other lanes of this wave
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_fence();  // the private vector is read by other lanes of this wave
     return tv;
 }
 
+// a -= v_r conj(w_c) + w_r conj(v_c)   (the rank-2 update of one matrix entry, 8 FMAs)
+__device__ __forceinline__ void hr_rank2(double2& a, double2 vr, double2 wr, double2 vc, double2 wc) {
+    a.x = fma(-vr.x, wc.x, a.x);
+    a.x = fma(-vr.y, wc.y, a.x);
+    a.x = fma(-wr.x, vc.x, a.x);
+    a.x = fma(-wr.y, vc.y, a.x);
+    a.y = fma(-vr.y, wc.x, a.y);
+    a.y = fma(vr.x, wc.y, a.y);
+    a.y = fma(-wr.y, vc.x, a.y);
+    a.y = fma(wr.x, vc.y, a.y);
+}
+
 __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
-    __shared__ double2 vpriv[HR_NW][HR_N];
+    __shared__ double2 vpriv[2][HR_NW][HR_N];
     __shared__ double2 rowold[2][HR_N];
     __shared__ double2 ww[HR_N];
-    __shared__ double2 pbuf[4 * HR_N];
+    __shared__ double2 pbuf[HR_NCB * HR_N];
     __shared__ double2 dotp[2];
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
     const int n = w.gsz[j], tid = threadIdx.x;
     const int wv = tid >> 6, lane = tid & 63;
-    const int rh = wv >> 2, cb = wv & 3;
-    const int r = rh * 64 + lane, c0 = cb * 32;
+    const int rh = wv / HR_NCB, cb = wv % HR_NCB;
+    const int r = rh * 64 + lane, c0 = cb * HR_CW;
     const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
     double* dd = w.dd + (size_t)j * w.nmax;
     double* ee = w.ee + (size_t)j * w.nmax;
     double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
     double2* tau = w.tau + (size_t)j * w.nmax;
-    double2* vp = vpriv[wv];
-    double2 a[32];
+    double2 a[HR_CW];
 #pragma unroll
-    for (int t = 0; t < 32; ++t) {
+    for (int t = 0; t < HR_CW; ++t) {
         const int c = c0 + t;
         double2 v = mk(0.0, 0.0);
         if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
@@ -492,44 +528,44 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
         }
         return;
     }
-    // reflector 0 from the unreduced row 0
+    // every LDS vector starts finite: the branch-free tile pass multiplies stale entries by zero
+    for (int e = tid; e < HR_N; e += HR_NT) ww[e] = mk(0.0, 0.0);
+    for (int e = tid; e < 2 * HR_NW * HR_N; e += HR_NT) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
+    // reflector 0 from the unreduced row 0, partial A v_0, row 1 published
     if (r == 0) {
 #pragma unroll
-        for (int t = 0; t < 32; ++t) rowold[0][c0 + t] = a[t];
+        for (int t = 0; t < HR_CW; ++t) rowold[0][c0 + t] = a[t];
     }
     __syncthreads();
-    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vp, wv == 0, dd, ee, tau,
+    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vpriv[0][wv], wv == 0, dd, ee, tau,
                               refl);
+    {
+        double2 acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < HR_CW; ++t) cfma(acc, a[t], vpriv[0][wv][c0 + t]);
+        pbuf[cb * HR_N + r] = acc;
+        if (r == 1) {
+#pragma unroll
+            for (int t = 0; t < HR_CW; ++t) rowold[1][c0 + t] = a[t];
+        }
+    }
     for (int i = 0; i + 1 < n; ++i) {
-        const int buf = (i + 1) & 1;
-        const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
-        const bool rows_live = (rh * 64 + 63 > i) && (rh * 64 < n);
-        const bool cols_live = (c0 + 31 > i) && (c0 < n);
-        // partial p_r over this column block; the owner publishes row i+1 before the update
-        if (act) {
-            double2 acc = mk(0.0, 0.0);
-            if (rows_live && cols_live) {
-#pragma unroll
-                for (int t = 0; t < 32; ++t) cfma(acc, a[t], vp[c0 + t]);
-            }
-            pbuf[cb * HR_N + r] = acc;
-        }
-        if (r == i + 1) {
-#pragma unroll
-            for (int t = 0; t < 32; ++t) rowold[buf][c0 + t] = a[t];
-        }
+        const double2* vc_ = vpriv[i & 1][wv];
+        double2* vn_ = vpriv[(i + 1) & 1][wv];
         __syncthreads();  // (B)
+        const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
         if (act && cb == 0) {
             double2 q = mk(0.0, 0.0);
             double2 pr = mk(0.0, 0.0);
             if (r > i && r < n) {
-                pr = cadd(cadd(pbuf[r], pbuf[HR_N + r]), cadd(pbuf[2 * HR_N + r], pbuf[3 * HR_N + r]));
+#pragma unroll
+                for (int b = 0; b < HR_NCB; ++b) pr = cadd(pr, pbuf[b * HR_N + r]);
                 pr = cmul(tv, pr);
-                cfmac(q, pr, vp[r]);
+                cfmac(q, pr, vc_[r]);
             }
             ww[r] = pr;  // zero outside (i, n)
-            q.x = wave_sum(q.x);
-            q.y = wave_sum(q.y);
+            q.x = wave_sum_dpp(q.x);
+            q.y = wave_sum_dpp(q.y);
             if (lane == 0) dotp[rh] = q;
         }
         __syncthreads();  // (C)
@@ -537,53 +573,31 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
         if (act) {
             const double2 a2t = cmul(tv, cadd(dotp[0], dotp[1]));
             a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
-            if (rows_live && cols_live && r > i && r < n) {
-                const double2 vr = vp[r];
-                double2 wr = ww[r];
-                cfma(wr, a2, vr);
-                // a[t] -= v_r conj(w_c) + w_r conj(v_c)
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const double2 vc = vp[c0 + t];
-                    double2 wc = ww[c0 + t];
-                    cfma(wc, a2, vc);
-                    const double2 u1 = cmulc(wc, vr);
-                    const double2 u2 = cmulc(vc, wr);
-                    a[t].x -= u1.x + u2.x;
-                    a[t].y -= u1.y + u2.y;
-                }
-            }
         }
-        // row i+1 after this update (the same arithmetic as the owner's), then reflector i+1
-        double2 x0 = rowold[buf][lane], x1 = rowold[buf][lane + 64];
+        // row i+1 after update i (every wave), then reflector i+1
+        double2 x0 = rowold[(i + 1) & 1][lane], x1 = rowold[(i + 1) & 1][lane + 64];
         if (act) {
-            const int rn = i + 1;
-            const double2 vr = vp[rn];
-            double2 wr = ww[rn];
+            const double2 vr = vc_[i + 1];
+            double2 wr = ww[i + 1];
             cfma(wr, a2, vr);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int c = lane + 64 * h;
-                if (c > i && c < n) {
-                    const double2 vc = vp[c];
-                    double2 wc = ww[c];
-                    cfma(wc, a2, vc);
-                    const double2 u1 = cmulc(wc, vr);
-                    const double2 u2 = cmulc(vc, wr);
-                    double2& x = h == 0 ? x0 : x1;
-                    x.x -= u1.x + u2.x;
-                    x.y -= u1.y + u2.y;
-                }
+            if (lane > i && lane < n) {
+                const double2 vc = vc_[lane];
+                double2 wc = ww[lane];
+                cfma(wc, a2, vc);
+                hr_rank2(x0, vr, wr, vc, wc);
+            }
+            if (lane + 64 > i && lane + 64 < n) {
+                const double2 vc = vc_[lane + 64];
+                double2 wc = ww[lane + 64];
+                cfma(wc, a2, vc);
+                hr_rank2(x1, vr, wr, vc, wc);
             }
         }
-        // every lane has read v_i (vp) above before the reflector overwrites it
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (i + 2 < n) {
-            tv = hr_reflector(i + 1, n, lane, x0, x1, vp, wv == 0, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
+        const bool more = i + 2 < n;
+        double2 tvn = mk(0.0, 0.0);
+        if (more) {
+            tvn = hr_reflector(i + 1, n, lane, x0, x1, vn_, wv == 0, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
         } else if (wv == 0) {
-            // last diagonal entry
             const double2 xd = (n - 1) < 64 ? x0 : x1;
             const double dl = readlane_f64(xd.x, (n - 1) & 63);
             if (lane == 0) {
@@ -591,6 +605,41 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
                 ee[n - 1] = 0.0;
             }
         }
+        // one pass over the tile: update i, then the partial A v_{i+1} of step i+1.  Branch-free
+        // inside (rows outside (i, n) update with v_r = w_r = 0, which leaves them unchanged), so
+        // the compiler can batch the LDS reads instead of waiting on each one.
+        const bool rows_live = (rh * 64 + 63 > i) && (rh * 64 < n);
+        const bool cols_live = (c0 + HR_CW - 1 > i) && (c0 < n);
+        double2 acc = mk(0.0, 0.0);
+        if (rows_live && cols_live) {  // uniform per wave
+            const bool upd = act && r > i && r < n;
+            double2 vr = vc_[r], wr = ww[r];
+            cfma(wr, a2, vr);
+            if (!upd) {
+                vr = mk(0.0, 0.0);
+                wr = mk(0.0, 0.0);
+            }
+            double2 acc1 = mk(0.0, 0.0);
+#pragma unroll
+            for (int t = 0; t < HR_CW; ++t) {
+                const double2 vc = vc_[c0 + t];
+                double2 wc = ww[c0 + t];
+                const double2 vn = vn_[c0 + t];
+                cfma(wc, a2, vc);
+                hr_rank2(a[t], vr, wr, vc, wc);
+                if (t & 1) cfma(acc1, a[t], vn);
+                else cfma(acc, a[t], vn);
+            }
+            acc = cadd(acc, acc1);
+        }
+        if (more) {
+            pbuf[cb * HR_N + r] = acc;
+            if (r == i + 2) {
+#pragma unroll
+                for (int t = 0; t < HR_CW; ++t) rowold[i & 1][c0 + t] = a[t];
+            }
+        }
+        tv = tvn;
     }
 }
 
