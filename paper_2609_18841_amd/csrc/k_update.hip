@@ -460,10 +460,11 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
     } else {
         const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
         beta = alpha.x >= 0.0 ? -nrm : nrm;
-        tv = mk((beta - alpha.x) / beta, -alpha.y / beta);
+        const double ib = 1.0 / beta;
+        tv = mk((beta - alpha.x) * ib, -alpha.y * ib);
         const double2 z = mk(alpha.x - beta, alpha.y);
-        const double den = z.x * z.x + z.y * z.y;
-        sc = mk(z.x / den, -z.y / den);
+        const double iden = 1.0 / (z.x * z.x + z.y * z.y);
+        sc = mk(z.x * iden, -z.y * iden);
     }
     const double2 v0 = (c0 > i && c0 < n) ? ((c0 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x0), sc)) : mk(0.0, 0.0);
     const double2 v1 = (c1 > i && c1 < n) ? ((c1 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x1), sc)) : mk(0.0, 0.0);
@@ -637,6 +638,170 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
             if (r == i + 2) {
 #pragma unroll
                 for (int t = 0; t < HR_CW; ++t) rowold[i & 1][c0 + t] = a[t];
+            }
+        }
+        tv = tvn;
+    }
+}
+
+// MFMA variant for n <= 128 (512 threads = 8 waves, one item per workgroup).  Wave bj owns the
+// block column of columns 16 bj .. 16 bj + 15 over all 128 rows, held as eight 16 x 16 blocks in
+// the FP64 MFMA accumulator layout (lane l, element k: row l/16 + 4k, column l%16), real and
+// imaginary parts apart.  Per step:
+//   p = tau A v for the wave's own 16 indices from the column sums of its blocks (A is
+//   Hermitian: p_c = sum_r conj(A_rc) v_r), i.e. per-lane products and a 4-group exchange, so p
+//   needs no exchange between waves; p^+ v is summed over waves (barrier 1);
+//   w = p - (tau/2)(p^+ v) v is published for all indices (barrier 2);
+//   every wave forms the updated row i+1 and from it reflector i+1 (as in k_hetrd_tile);
+//   the rank-2 update A -= v w^+ + w v^+ of each live block is two MFMA 16x16x4 products
+//   (real and imaginary part) with [v_r, w_r] as the 16 x 4 operand and [w_c; v_c] as 4 x 16.
+typedef double hm_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double hm_pick(int g, double a0, double a1, double a2, double a3) {
+    return g == 0 ? a0 : (g == 1 ? a1 : (g == 2 ? a2 : a3));
+}
+
+__global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
+    __shared__ double2 vpriv[2][HR_NW][HR_N];
+    __shared__ double2 rowold[2][HR_N];
+    __shared__ double2 ww[HR_N];
+    __shared__ double2 qpart[HR_NW];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    const int n = w.gsz[j], tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, cl = lane & 15;
+    const int C0 = 16 * wv, myc = C0 + cl;
+    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+    double* dd = w.dd + (size_t)j * w.nmax;
+    double* ee = w.ee + (size_t)j * w.nmax;
+    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    double2* tau = w.tau + (size_t)j * w.nmax;
+    hm_d4 are[8], aim[8];
+#pragma unroll
+    for (int bi = 0; bi < 8; ++bi) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int r = 16 * bi + g + 4 * k, c = myc;
+            double2 v = mk(0.0, 0.0);
+            if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
+            are[bi][k] = v.x;
+            aim[bi][k] = v.y;
+        }
+    }
+    if (n == 1) {
+        if (tid == 0) {
+            dd[0] = are[0][0];
+            ee[0] = 0.0;
+        }
+        return;
+    }
+    for (int e = tid; e < HR_N; e += HR_NT) ww[e] = mk(0.0, 0.0);
+    for (int e = tid; e < 2 * HR_NW * HR_N; e += HR_NT) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
+    // row 0: block 0, local row 0 (g = 0, k = 0) of every wave
+    if (g == 0) rowold[0][myc] = mk(are[0][0], aim[0][0]);
+    __syncthreads();
+    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vpriv[0][wv], wv == 0, dd, ee, tau,
+                              refl);
+    const bool cols_live0 = C0 < n;
+    for (int i = 0; i + 1 < n; ++i) {
+        const double2* vc_ = vpriv[i & 1][wv];
+        double2* vn_ = vpriv[(i + 1) & 1][wv];
+        const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
+        const bool cols_live = cols_live0 && (C0 + 15 > i);
+        // p_c = tau sum_r conj(A_rc) v_r for the wave's columns c = C0 + cl
+        double pr = 0.0, pim = 0.0;
+        if (act && cols_live) {
+#pragma unroll
+            for (int bi = 0; bi < 8; ++bi) {
+                if (16 * bi + 15 > i && 16 * bi < n) {  // uniform
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const double2 vr = vc_[16 * bi + g + 4 * k];
+                        // conj(a) v
+                        pr = fma(are[bi][k], vr.x, pr);
+                        pr = fma(aim[bi][k], vr.y, pr);
+                        pim = fma(are[bi][k], vr.y, pim);
+                        pim = fma(-aim[bi][k], vr.x, pim);
+                    }
+                }
+            }
+            // sum over the four row groups (lanes cl, cl+16, cl+32, cl+48)
+            pr += __shfl_xor(pr, 16);
+            pim += __shfl_xor(pim, 16);
+            pr += __shfl_xor(pr, 32);
+            pim += __shfl_xor(pim, 32);
+        }
+        const double2 pc = (act && myc > i && myc < n) ? cmul(tv, mk(pr, pim)) : mk(0.0, 0.0);
+        if (act) {
+            double2 qp = mk(0.0, 0.0);
+            if (g == 0) cfmac(qp, pc, vc_[myc]);
+            qp.x = wave_sum_dpp(qp.x);
+            qp.y = wave_sum_dpp(qp.y);
+            if (lane == 0) qpart[wv] = qp;
+        }
+        // every wave publishes its 16 entries of row i+1 as they are before update i
+        {
+            const int rl = (i + 1) & 15, bi0 = (i + 1) >> 4;
+            if (g == (rl & 3)) {
+                const int k0 = rl >> 2;
+                double xr = 0.0, xi = 0.0;
+#pragma unroll
+                for (int bi = 0; bi < 8; ++bi)
+                    if (bi == bi0) {
+                        xr = hm_pick(k0, are[bi][0], are[bi][1], are[bi][2], are[bi][3]);
+                        xi = hm_pick(k0, aim[bi][0], aim[bi][1], aim[bi][2], aim[bi][3]);
+                    }
+                rowold[(i + 1) & 1][myc] = mk(xr, xi);
+            }
+        }
+        __syncthreads();  // (1)
+        double2 a2 = mk(0.0, 0.0);
+        if (act) {
+            double2 q = mk(0.0, 0.0);
+#pragma unroll
+            for (int b = 0; b < HR_NW; ++b) q = cadd(q, qpart[b]);
+            const double2 a2t = cmul(tv, q);
+            a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
+            if (g == 0) {
+                double2 wc = pc;
+                cfma(wc, a2, vc_[myc]);
+                ww[myc] = wc;  // zero outside (i, n)
+            }
+        }
+        __syncthreads();  // (2)
+        // row i+1 after update i (every wave), then reflector i+1
+        double2 x0 = rowold[(i + 1) & 1][lane], x1 = rowold[(i + 1) & 1][lane + 64];
+        if (act) {
+            const double2 vr = vc_[i + 1], wr = ww[i + 1];
+            if (lane > i && lane < n) hr_rank2(x0, vr, wr, vc_[lane], ww[lane]);
+            if (lane + 64 > i && lane + 64 < n) hr_rank2(x1, vr, wr, vc_[lane + 64], ww[lane + 64]);
+        }
+        double2 tvn = mk(0.0, 0.0);
+        if (i + 2 < n) {
+            tvn = hr_reflector(i + 1, n, lane, x0, x1, vn_, wv == 0, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
+        } else if (wv == 0) {
+            const double2 xd = (n - 1) < 64 ? x0 : x1;
+            const double dl = readlane_f64(xd.x, (n - 1) & 63);
+            if (lane == 0) {
+                dd[n - 1] = dl;
+                ee[n - 1] = 0.0;
+            }
+        }
+        // rank-2 update of the live blocks on MFMA: D += X Y with X = rows of block bi, Y = this column block
+        if (act && cols_live) {
+            const double2 wc = ww[myc], vc = vc_[myc];
+            const double y = hm_pick(g, wc.x, wc.y, vc.x, vc.y);
+#pragma unroll
+            for (int bi = 0; bi < 8; ++bi) {
+                if (16 * bi + 15 > i && 16 * bi < n) {  // uniform
+                    const double2 vr = vc_[16 * bi + cl], wr = ww[16 * bi + cl];
+                    const double xre = hm_pick(g, -vr.x, -vr.y, -wr.x, -wr.y);
+                    const double xim = hm_pick(g, -vr.y, vr.x, -wr.y, wr.x);
+                    are[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(xre, y, are[bi], 0, 0, 0);
+                    aim[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(xim, y, aim[bi], 0, 0, 0);
+                }
             }
         }
         tv = tvn;
@@ -1516,7 +1681,7 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
     prof_end(prof, TN_K_GRAM, st);
     prof_begin(prof, TN_K_HETRD, st);
     if (w.nmax <= HR_N)
-        hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+        hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
     else if (w.nmax <= HETRD_LDS_N)
         hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
     else
