@@ -30,7 +30,7 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 # sources it was taken with, and its figures are used only while the sources still match.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_qsd_B256_L64_chi64_split.txt")
 # timing bucket -> the kernel that runs in it for this workload (split precision, n = 128, chi = 64)
-BUCKET_KERNEL = {"gram": "k_gram", "hetrd": "k_hetrd_tile", "vecs": "k_vecs_fast", "split": "k_split"}
+BUCKET_KERNEL = {"gram": "k_gram", "hetrd": "k_hetrd_mfma", "vecs": "k_tvecs", "steqr": "k_bisect", "split": "k_split"}
 
 # algorithmic FLOPs per two-site update at the workload shape (m = n = 128, chi_m = k = 64, D = 4)
 def algo_flops(n=128, m=128, chim=64, k=64, D=4):

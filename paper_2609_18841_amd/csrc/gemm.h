@@ -1,5 +1,6 @@
 // Block-level complex GEMM core used by the Theta, Gram, split and measurement
-// kernels.  One 256-thread workgroup computes a BM x BN tile of
+// kernels.  Complex64 operands run on the FP32 matrix cores (block_gemm_mfma_c32); complex128
+// operands on the vector ALU as described here.  One 256-thread workgroup computes a BM x BN tile of
 //     C(m, n) = sum_k A(m, k) * B(k, n)
 // where A and B are supplied by load functors (so transposition, conjugation,
 // row weights and gathered physical indices cost nothing extra) and the result
@@ -8,12 +9,94 @@
 // reads).  A_KFAST / B_NFAST select the global-load order so that consecutive
 // lanes touch consecutive addresses for the operand's storage order.
 #pragma once
+#include <type_traits>
 #include "common.h"
+
+typedef float gemm_f4 __attribute__((ext_vector_type(4)));
+
+template <class Acc, bool A_KFAST, bool B_NFAST, int BK, class LA, class LB>
+__device__ __forceinline__ void gemm_stage(int M, int N, int K, int m0, int n0, int k0, LA la, LB lb, Acc* As,
+                                           Acc* Bs) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e0 = 0; e0 < 64 * BK; e0 += 256) {
+        int e = e0 + tid;
+        int mm, kk;
+        if (A_KFAST) { mm = e / BK; kk = e % BK; } else { kk = e / 64; mm = e % 64; }
+        int gm = m0 + mm, gk = k0 + kk;
+        As[kk * 64 + mm] = (gm < M && gk < K) ? la(gm, gk) : czero<Acc>();
+    }
+#pragma unroll
+    for (int e0 = 0; e0 < 64 * BK; e0 += 256) {
+        int e = e0 + tid;
+        int nn, kk;
+        if (B_NFAST) { kk = e / 64; nn = e % 64; } else { nn = e / BK; kk = e % BK; }
+        int gn = n0 + nn, gk = k0 + kk;
+        Bs[kk * 64 + nn] = (gn < N && gk < K) ? lb(gk, gn) : czero<Acc>();
+    }
+}
+
+// Complex64 tiles on the matrix cores: each of the 4 waves owns a 32 x 32 quarter of the
+// 64 x 64 tile as 2 x 2 blocks of 16 x 16; a k-step of 4 is four real MFMA 16x16x4 f32
+// products per block (re*re, -im*im into the real part, re*im, im*re into the imaginary part),
+// accumulated in FP32.  Operand layouts: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element r of lane l is C[4*(l/16) + r][l%16].
+template <bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
+__device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
+                                                    float2* As, float2* Bs) {
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    gemm_f4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cr[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+            ci[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+        }
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        gemm_stage<float2, A_KFAST, B_NFAST, BK>(M, N, K, m0, n0, k0, la, lb, As, Bs);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            float2 av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[(kk + lk) * 64 + wm + 16 * a + li];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[(kk + lk) * 64 + wn + 16 * b + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+                    cr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av[a].y, bv[b].y, cr[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+                    ci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + 16 * a + 4 * lk + r, gn = n0 + wn + 16 * b + li;
+                if (gm < M && gn < N) sc(gm, gn, make_float2(cr[a][b][r], ci[a][b][r]));
+            }
+}
 
 template <class Acc, bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
 __device__ __forceinline__ void block_gemm(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
                                            Acc* As /* BK*64 */, Acc* Bs /* BK*64 */)
 {
+    if constexpr (std::is_same<Acc, float2>::value) {
+        static_assert(BK % 4 == 0, "MFMA k-steps of 4");
+        block_gemm_mfma_c32<A_KFAST, B_NFAST, BK>(M, N, K, m0, n0, la, lb, sc, As, Bs);
+        return;
+    } else {
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
     Acc acc[4][4];
@@ -62,4 +145,5 @@ __device__ __forceinline__ void block_gemm(int M, int N, int K, int m0, int n0, 
             int gm = m0 + ty + 16 * r, gn = n0 + tx + 16 * c;
             if (gm < M && gn < N) sc(gm, gn, acc[r][c]);
         }
+    }
 }
