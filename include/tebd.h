@@ -157,6 +157,15 @@ int mps_replicate(void* s, int src);
  * basis (m_b, m_{b+1}).  out: 16 or 256 complex. */
 int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 
+/* ---- graph replay --------------------------------------------------------- */
+
+/* tebd_step replays one captured HIP graph per Trotter order (all layers of one step, kernel
+ * launches only) for unmasked steps while timing is off and the stream given to mps_alloc is a
+ * created (non-null) stream; otherwise it launches eagerly.  Both give identical results.
+ * on = 0 switches replay off and releases the captured graphs; on = 1 (the default) allows it.
+ * Returns TN_OK or TN_EINVAL (null handle). */
+int tn_graph_enable(void* s, int on);
+
 /* ---- kernel timing (HIP events on the library stream) -------------------- */
 #define TN_K_THETA   0  /* Theta formation + gate */
 #define TN_K_GRAM    1  /* weighted Gram matrix */

@@ -103,7 +103,9 @@ class State:
         if nbytes == 0:
             raise TnError(-1, "invalid shape for mps_arena_bytes")
         self.arena = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        # a created stream (default priority) of its own: tebd_step can then capture and replay
+        # HIP graphs; every entry point synchronizes it before returning host outputs
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
         occ = np.ascontiguousarray(np.asarray(init_occ, dtype=np.int32))
         self._mstruct = model.struct()
         h = ctypes.c_void_p()
@@ -191,6 +193,10 @@ class State:
     # ---- timing
     def prof_enable(self, on=True):
         _check(self.lib.tn_prof_enable(self.h, 1 if on else 0))
+
+    def graph_enable(self, on=True):
+        """Allow (default) or forbid HIP-graph replay of unmasked Trotter steps."""
+        _check(self.lib.tn_graph_enable(self.h, 1 if on else 0))
 
     def prof_query(self, kid):
         ms = ctypes.c_double()

@@ -86,7 +86,18 @@ struct tn_state {
     double slot_tau[2];
     bool slot_valid[2];
     Prof prof;
+    // one captured Trotter step (all layers, unmasked) per order, replayed by tebd_step
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    int use_graph = 1;
 };
+
+static void drop_graphs(tn_state* s) {
+    for (int o = 0; o < 3; ++o)
+        if (s->gexec[o]) {
+            hipGraphExecDestroy(s->gexec[o]);
+            s->gexec[o] = nullptr;
+        }
+}
 
 static inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -370,6 +381,7 @@ extern "C" int mps_free(void* h) {
             hipEventDestroy(pr.first);
             hipEventDestroy(pr.second);
         }
+    drop_graphs(s);
     delete s;
     return TN_OK;
 }
@@ -632,9 +644,35 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_mask, mask, s->B, hipMemcpyHostToDevice, s->stream));
         mdev = reinterpret_cast<const unsigned char*>(s->arena + s->lay.off_mask);
     }
-    for (int st = 0; st < n_steps; ++st)
-        for (auto& ly : layers)
-            if ((rc = run_layer(s, ly.first, ly.second, mdev))) return rc;
+    // Unmasked, untimed steps replay one captured graph of the step's layers (kernel launches
+    // only: no memset or copy nodes); gates live in fixed arena slots, so a new dt needs no
+    // re-capture.  The library's stream must be a created stream for capture.
+    if (s->use_graph && !mdev && !s->prof.on && s->stream != nullptr && n_steps > 0) {
+        if (!s->gexec[order]) {
+            HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            int crc = TN_OK;
+            for (auto& ly : layers)
+                if ((crc = run_layer(s, ly.first, ly.second, nullptr))) break;
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(s->stream, &graph);
+            if (crc) {
+                if (graph) hipGraphDestroy(graph);
+                return crc;
+            }
+            if (ce != hipSuccess) return fail(TN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+            const hipError_t ie = hipGraphInstantiate(&s->gexec[order], graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                s->gexec[order] = nullptr;
+                return fail(TN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+        }
+        for (int st = 0; st < n_steps; ++st) HIPCHK(hipGraphLaunch(s->gexec[order], s->stream));
+    } else {
+        for (int st = 0; st < n_steps; ++st)
+            for (auto& ly : layers)
+                if ((rc = run_layer(s, ly.first, ly.second, mdev))) return rc;
+    }
     if ((rc = check_flags(s))) {
         if (trunc_weight_out)
             hipMemcpy(trunc_weight_out, s->arena + s->lay.off_trunc, (size_t)s->B * 8, hipMemcpyDeviceToHost);
@@ -793,6 +831,16 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
     }
     prof_end(&s->prof, TN_K_JUMPS, s->stream);
     HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ graph replay switch
+extern "C" int tn_graph_enable(void* h, int on) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    hipStreamSynchronize(s->stream);
+    s->use_graph = on != 0;
+    if (!s->use_graph) drop_graphs(s);
     return TN_OK;
 }
 
