@@ -157,6 +157,16 @@ int mps_replicate(void* s, int src);
  * basis (m_b, m_{b+1}).  out: 16 or 256 complex. */
 int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 
+/* ---- autotuner -------------------------------------------------------------- */
+
+/* For n <= 128 the Householder reduction has two kernels (FP64 MFMA block columns = 0, wave
+ * tiles = 1).  The first tebd_step of a state times both on the Gram matrices of its own first
+ * chunk (median of three) and keeps the faster one.  tn_tuning reports the choice
+ * (variant_out, may be NULL) and the median times in ms (ms_out[2], may be NULL; zero before
+ * tuning or when n > 128); set_variant 0 or 1 overrides the choice, -1 only reports.
+ * Returns TN_OK or TN_EINVAL. */
+int tn_tuning(void* s, int set_variant, int* variant_out, float* ms_out);
+
 /* ---- graph replay --------------------------------------------------------- */
 
 /* tebd_step replays one captured HIP graph per Trotter order (all layers of one step, kernel

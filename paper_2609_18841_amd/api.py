@@ -194,6 +194,13 @@ class State:
     def prof_enable(self, on=True):
         _check(self.lib.tn_prof_enable(self.h, 1 if on else 0))
 
+    def tuning(self, set_variant=-1):
+        """(variant, [ms_mfma, ms_tiles]) of the Householder autotuner; set_variant 0/1 overrides."""
+        v = ctypes.c_int()
+        ms = (ctypes.c_float * 2)()
+        _check(self.lib.tn_tuning(self.h, int(set_variant), ctypes.byref(v), ms))
+        return v.value, [ms[0], ms[1]]
+
     def graph_enable(self, on=True):
         """Allow (default) or forbid HIP-graph replay of unmasked Trotter steps."""
         _check(self.lib.tn_graph_enable(self.h, 1 if on else 0))

@@ -105,6 +105,7 @@ struct DevWork {
     int jacobi;                  // 1: one-sided Jacobi refinement of the SVD (FP64 mode)
     double* lsel;                // items * nmax  selected eigenvalues, descending (bisection path)
     int* fb;                     // items  1: item takes the logged-QL eigenvector path, or null
+    int hvar;                    // Householder kernel for n <= 128: 0 MFMA block columns, 1 wave tiles
     double2* Y;                  // items * ysz  Y = Theta~ V, column-major m x r (aliases the Gram slot)
     int ldy;                     // leading dimension of Y (>= mmax)
     size_t ysz;                  // elements per item

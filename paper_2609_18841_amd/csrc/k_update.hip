@@ -1680,7 +1680,9 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
     if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_GRAM, st);
     prof_begin(prof, TN_K_HETRD, st);
-    if (w.nmax <= HR_N)
+    if (w.nmax <= HR_N && w.hvar == 1)
+        hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+    else if (w.nmax <= HR_N)
         hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
     else if (w.nmax <= HETRD_LDS_N)
         hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
@@ -1739,6 +1741,29 @@ void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream
         launch_layer_chunk_t<double2>(s, w, st, prof, glog, gwt);
     else
         launch_layer_chunk_t<float2>(s, w, st, prof, glog, gwt);
+}
+
+template <class T>
+static void launch_update_prefix_t(const DevState& s, const DevWork& w, hipStream_t st) {
+    const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
+    hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+    hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
+}
+
+void launch_update_prefix(int prec, const DevState& s, const DevWork& w, hipStream_t st) {
+    if (prec == 0)
+        launch_update_prefix_t<double2>(s, w, st);
+    else
+        launch_update_prefix_t<float2>(s, w, st);
+}
+
+void launch_hetrd_variant(const DevState& s, const DevWork& w, int variant, hipStream_t st) {
+    if (variant == 1)
+        hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+    else
+        hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
 }
 
 void launch_reduce_items(const DevState& s, int nb, int parity, const unsigned char* mask, const double* glog,

@@ -28,6 +28,10 @@ void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream
                         double* glog, double* gwt);
 void launch_reduce_items(const DevState& s, int nb, int parity, const unsigned char* mask, const double* glog,
                          const double* gwt, hipStream_t st);
+// pieces of the pipeline used by the autotuner: Theta, gate and Gram of a chunk (pure functions
+// of the state), and one Householder variant on that Gram (workspace only)
+void launch_update_prefix(int prec, const DevState& s, const DevWork& w, hipStream_t st);
+void launch_hetrd_variant(const DevState& s, const DevWork& w, int variant, hipStream_t st);
 
 // measurement workspace for a chunk of instances (k_measure.hip)
 struct MeasWork {

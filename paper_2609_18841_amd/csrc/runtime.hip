@@ -89,6 +89,10 @@ struct tn_state {
     // one captured Trotter step (all layers, unmasked) per order, replayed by tebd_step
     hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
     int use_graph = 1;
+    // autotuner: Householder variant for n <= 128 chosen by timing on the state's own data
+    int tuned = 0;
+    int hvar = 0;
+    float tune_ms[2] = {0.0f, 0.0f};
 };
 
 static void drop_graphs(tn_state* s) {
@@ -562,61 +566,108 @@ static int check_flags(tn_state* s) {
 }
 
 // ------------------------------------------------------------------ TEBD
+// workspace view of the chunk of items [i0, i0 + nitems) of one layer
+static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, int nitems,
+                          const unsigned char* mask_dev) {
+    char* ws = s->arena + s->lay.off_ws;
+    DevWork w;
+    w.item0 = (int)i0;
+    w.nitems = nitems;
+    w.parity = parity;
+    w.nb = nb;
+    w.mask = mask_dev;
+    w.gates = reinterpret_cast<const double2*>(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16);
+    w.gstride = s->gstride;
+    w.mmax = s->mmax;
+    w.nmax = s->nmax;
+    w.theta_stride = (size_t)s->mmax * s->nmax;
+    w.theta = ws + s->lay.u_theta;
+    w.gram = reinterpret_cast<double2*>(ws + s->lay.u_gram);
+    w.refl = reinterpret_cast<double2*>(ws + s->lay.u_refl);
+    w.tau = reinterpret_cast<double2*>(ws + s->lay.u_tau);
+    w.dd = reinterpret_cast<double*>(ws + s->lay.u_dd);
+    w.ee = reinterpret_cast<double*>(ws + s->lay.u_ee);
+    w.logcap = s->logcap;
+    w.logi = reinterpret_cast<int*>(ws + s->lay.u_logi);
+    w.logcs = reinterpret_cast<double2*>(ws + s->lay.u_logcs);
+    w.nrot = reinterpret_cast<int*>(ws + s->lay.u_nrot);
+    w.sel = reinterpret_cast<int*>(ws + s->lay.u_sel);
+    w.kout = reinterpret_cast<int*>(ws + s->lay.u_kout);
+    w.sout = reinterpret_cast<double*>(ws + s->lay.u_sout);
+    w.wout = reinterpret_cast<double*>(ws + s->lay.u_wout);
+    w.V = reinterpret_cast<double2*>(ws + s->lay.u_V);
+    w.zscratch = reinterpret_cast<double2*>(ws + s->lay.u_z);
+    w.pscratch = reinterpret_cast<double2*>(ws + s->lay.u_p);
+    w.flags = at<int>(s, s->lay.off_flags);
+    w.gsz = reinterpret_cast<int*>(ws + s->lay.u_gsz);
+    w.qra = reinterpret_cast<double2*>(ws + s->lay.u_qra);
+    w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
+    w.qr_route = s->prec == 0 ? 1 : 0;
+    w.jacobi = s->prec == 0 ? 1 : 0;
+    w.vld = s->prec == 0 ? s->nmax : s->chi;
+    w.Y = w.gram;  // the Gram slot is free once the Householder reduction has read it
+    w.ldy = s->nmax;
+    w.ysz = (size_t)s->nmax * s->nmax;
+    w.lsel = reinterpret_cast<double*>(ws + s->lay.u_lsel);
+    // split mode with n <= 128 and chi <= 64 takes the bisection path (kernels in k_update.hip)
+    w.fb = (s->prec == 1 && s->nmax <= 128 && s->chi <= 64) ? reinterpret_cast<int*>(ws + s->lay.u_fb) : nullptr;
+    w.hvar = s->hvar;
+    return w;
+}
+
 static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mask_dev) {
     const int nb = parity <= s->L - 2 ? ((s->L - 2 - parity) / 2 + 1) : 0;
     if (nb == 0) return TN_OK;
     DevState ds = dev_state(s);
     const long total = (long)s->B * nb;
-    char* ws = s->arena + s->lay.off_ws;
     double* glog = at<double>(s, s->lay.off_glog);
     double* gwt = at<double>(s, s->lay.off_gwt);
     for (long i0 = 0; i0 < total; i0 += s->chunk) {
-        DevWork w;
-        w.item0 = (int)i0;
-        w.nitems = (int)std::min((long)s->chunk, total - i0);
-        w.parity = parity;
-        w.nb = nb;
-        w.mask = mask_dev;
-        w.gates = reinterpret_cast<const double2*>(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16);
-        w.gstride = s->gstride;
-        w.mmax = s->mmax;
-        w.nmax = s->nmax;
-        w.theta_stride = (size_t)s->mmax * s->nmax;
-        w.theta = ws + s->lay.u_theta;
-        w.gram = reinterpret_cast<double2*>(ws + s->lay.u_gram);
-        w.refl = reinterpret_cast<double2*>(ws + s->lay.u_refl);
-        w.tau = reinterpret_cast<double2*>(ws + s->lay.u_tau);
-        w.dd = reinterpret_cast<double*>(ws + s->lay.u_dd);
-        w.ee = reinterpret_cast<double*>(ws + s->lay.u_ee);
-        w.logcap = s->logcap;
-        w.logi = reinterpret_cast<int*>(ws + s->lay.u_logi);
-        w.logcs = reinterpret_cast<double2*>(ws + s->lay.u_logcs);
-        w.nrot = reinterpret_cast<int*>(ws + s->lay.u_nrot);
-        w.sel = reinterpret_cast<int*>(ws + s->lay.u_sel);
-        w.kout = reinterpret_cast<int*>(ws + s->lay.u_kout);
-        w.sout = reinterpret_cast<double*>(ws + s->lay.u_sout);
-        w.wout = reinterpret_cast<double*>(ws + s->lay.u_wout);
-        w.V = reinterpret_cast<double2*>(ws + s->lay.u_V);
-        w.zscratch = reinterpret_cast<double2*>(ws + s->lay.u_z);
-        w.pscratch = reinterpret_cast<double2*>(ws + s->lay.u_p);
-        w.flags = at<int>(s, s->lay.off_flags);
-        w.gsz = reinterpret_cast<int*>(ws + s->lay.u_gsz);
-        w.qra = reinterpret_cast<double2*>(ws + s->lay.u_qra);
-        w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
-        w.qr_route = s->prec == 0 ? 1 : 0;
-        w.jacobi = s->prec == 0 ? 1 : 0;
-        w.vld = s->prec == 0 ? s->nmax : s->chi;
-        w.Y = w.gram;  // the Gram slot is free once the Householder reduction has read it
-        w.ldy = s->nmax;
-        w.ysz = (size_t)s->nmax * s->nmax;
-        w.lsel = reinterpret_cast<double*>(ws + s->lay.u_lsel);
-        // split mode with n <= 128 and chi <= 64 takes the bisection path (kernels in k_update.hip)
-        w.fb = (s->prec == 1 && s->nmax <= 128 && s->chi <= 64) ? reinterpret_cast<int*>(ws + s->lay.u_fb) : nullptr;
+        const int nitems = (int)std::min((long)s->chunk, total - i0);
+        DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev);
         launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
         HIPCHK(hipGetLastError());
     }
     launch_reduce_items(ds, nb, parity, mask_dev, glog, gwt, s->stream);
     HIPCHK(hipGetLastError());
+    return TN_OK;
+}
+
+// Autotuner: for n <= 128 two Householder kernels exist (MFMA block columns, wave tiles).  On the
+// first Trotter step of a state both run on the Gram matrices of the state's own first chunk
+// (Theta, gate and Gram are recomputed by the real step, the Householder kernels write only
+// workspace), three times each, and the faster median is kept for the state's lifetime.
+static int autotune(tn_state* s, int slot) {
+    if (s->tuned) return TN_OK;
+    s->tuned = 1;
+    if (s->nmax > 128) return TN_OK;
+    const int nb = (s->L - 2) / 2 + 1;  // parity 0 bonds
+    const long total = (long)s->B * nb;
+    const int nitems = (int)std::min((long)s->chunk, total);
+    DevState ds = dev_state(s);
+    DevWork w = chunk_work(s, 0, nb, slot, 0, nitems, nullptr);
+    launch_update_prefix(s->prec, ds, w, s->stream);
+    HIPCHK(hipGetLastError());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float med[2];
+    for (int v = 0; v < 2; ++v) {
+        float t[3];
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, s->stream));
+            launch_hetrd_variant(ds, w, v, s->stream);
+            HIPCHK(hipEventRecord(e1, s->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&t[rep], e0, e1));
+        }
+        std::sort(t, t + 3);
+        med[v] = t[1];
+        s->tune_ms[v] = t[1];
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    s->hvar = med[1] < med[0] ? 1 : 0;
     return TN_OK;
 }
 
@@ -639,6 +690,7 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
         if ((rc = upload_gates(s, 1, dt))) return rc;
         layers = {{1, 0}, {0, 1}, {1, 0}};
     }
+    if (!s->tuned && n_steps > 0 && (rc = autotune(s, 0))) return rc;
     const unsigned char* mdev = nullptr;
     if (mask) {
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_mask, mask, s->B, hipMemcpyHostToDevice, s->stream));
@@ -831,6 +883,25 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
     }
     prof_end(&s->prof, TN_K_JUMPS, s->stream);
     HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
+// ------------------------------------------------------------------ autotuner report / override
+extern "C" int tn_tuning(void* h, int set_variant, int* variant_out, float* ms_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (set_variant < -1 || set_variant > 1) return fail(TN_EINVAL, "variant must be -1, 0 or 1");
+    if (set_variant >= 0) {
+        hipStreamSynchronize(s->stream);
+        s->hvar = set_variant;
+        s->tuned = 1;
+        drop_graphs(s);  // captured launches carry the old variant
+    }
+    if (variant_out) *variant_out = s->hvar;
+    if (ms_out) {
+        ms_out[0] = s->tune_ms[0];
+        ms_out[1] = s->tune_ms[1];
+    }
     return TN_OK;
 }
 
