@@ -58,6 +58,8 @@ extern "C" {
 #define TN_NOISE_GAUSS  0  /* dW = sqrt(dt) (x + i y)/sqrt(2), x, y ~ N(0,1) */
 #define TN_NOISE_BINARY 1  /* dW = eta sqrt(dt), eta = -1 if u < 1/2 else +1 (the paper's choice) */
 
+#define TN_MAX_JUMPS 256  /* jump channels per model */
+
 /* Model of Sec. 2.1: H = sum_b h_b with two-site terms h_b on sites (b, b+1),
  * and local jump operators L_k on site jump_site[k] with rate gamma[k]
  * (Sec. 1 eq. Lindblad; eq. LindbladLocal for how their -i/2 gamma L^+L parts are
@@ -66,7 +68,7 @@ typedef struct tn_model {
     int L;                    /* number of sites, >= 2 */
     int d;                    /* local Hilbert dimension; must be 2 */
     const double* h_bond;     /* (L-1) * 16 complex: 4x4 [out, in] in the basis n_b*2 + n_{b+1} */
-    int n_jumps;              /* 0 .. 8 */
+    int n_jumps;              /* 0 .. TN_MAX_JUMPS (e.g. dephasing on every site plus drives) */
     const int* jump_site;     /* n_jumps sites, 0-based */
     const double* jump_op;    /* n_jumps * 4 complex: 2x2 [out, in] local operator (no string) */
     const double* gamma;      /* n_jumps rates >= 0 */

@@ -63,6 +63,45 @@ def liouvillian(L, J=1.0, gamma=0.5, sink_string=True):
     return Lv.tocsr()
 
 
+def jump_ops_general(L, channels):
+    """Fermionic jump operators for a list of (kind, site, rate) channels (Sec. 2.1 mentions
+    these alternatives): kind "source" -> c_k^+, "sink" -> c_k (each with its Jordan-Wigner
+    string), "dephasing" -> n_k = c_k^+ c_k."""
+    c, cd = fermion_ops(L)
+    out = []
+    for kind, k, g in channels:
+        if kind == "source":
+            op = cd[k]
+        elif kind == "sink":
+            op = c[k]
+        elif kind == "dephasing":
+            op = (cd[k] @ c[k]).tocsr()
+        else:
+            raise ValueError(kind)
+        out.append((op, float(g)))
+    return out
+
+
+def liouvillian_general(L, channels, J=1.0):
+    """Vectorized generator of eq. (Lindblad) for an arbitrary list of channels (row-major vec)."""
+    D = 2 ** L
+    H = hamiltonian(L, J)
+    I = sp.identity(D, dtype=np.complex128, format="csr")
+    Lv = -1j * (sp.kron(H, I) - sp.kron(I, H.T))
+    for Lk, g in jump_ops_general(L, channels):
+        LdL = (Lk.conj().T @ Lk).tocsr()
+        Lv = Lv + g * (sp.kron(Lk, Lk.conj()) - 0.5 * sp.kron(LdL, I) - 0.5 * sp.kron(I, LdL.T))
+    return Lv.tocsr()
+
+
+def evolve_rho_general(occ, t, channels, J=1.0):
+    L = len(occ)
+    D = 2 ** L
+    v = product_rho(occ).reshape(-1)
+    v = spla.expm_multiply(liouvillian_general(L, channels, J) * t, v)
+    return v.reshape(D, D)
+
+
 def product_rho(occ):
     """rho(0) = |occ><occ| for an occupation-number product state."""
     L = len(occ)

@@ -82,3 +82,48 @@ def density_current(C):
     n = np.real(np.diag(C)).copy()
     j = np.array([np.real(1j * (C[i, i - 1] - C[i - 1, i])) for i in range(1, C.shape[0])])
     return n, j
+
+
+def c_exact_channels(t, occ, channels, J=1.0):
+    """C(t) for linear sources c_k^+, linear sinks c_k and dephasing n_k at arbitrary sites.
+
+    The channels extend eq. (eqCorr) term by term.
+    - Sources and sinks: each adds -(i/2) gamma_k P_k to K. A source also adds gamma_k e_k e_k^T to
+      Gamma. This is eq. (eqCorr) with the channel list of Sec. 2.1.
+    - Dephasing n_k: this is quadratic, so the equation stays closed.
+      -(gamma/2) [n_k, [n_k, c_i^+ c_j]] = -(gamma/2)(delta_ki - delta_kj)^2 c_i^+ c_j.
+      Off-diagonal entries therefore decay at (gamma_i + gamma_j)/2.
+
+        dC/dt = -i K C + i C K^+ + Gamma - D o C,   D_ij = (g_i + g_j)/2 (1 - delta_ij)
+
+    With row-major vec(C) this is a linear ODE dv/dt = M v + vec(Gamma). Here
+    M = -i (K (x) 1) + i (1 (x) K^*) - diag(vec D). It is integrated exactly by the exponential
+    of the augmented generator [[M, vec Gamma], [0, 0]].
+    """
+    L = len(occ)
+    K = np.zeros((L, L), dtype=np.complex128)
+    for i in range(L - 1):
+        K[i, i + 1] = J
+        K[i + 1, i] = J
+    G = np.zeros((L, L), dtype=np.complex128)
+    gph = np.zeros(L)
+    for kind, k, g in channels:
+        if kind in ("source", "sink"):
+            K[k, k] += -0.5j * g
+            if kind == "source":
+                G[k, k] += g
+        elif kind == "dephasing":
+            gph[k] += g
+        else:
+            raise ValueError(kind)
+    Dm = 0.5 * (gph[:, None] + gph[None, :]) * (1.0 - np.eye(L))
+    I = np.eye(L)
+    M = -1j * np.kron(K, I) + 1j * np.kron(I, K.conj()) - np.diag(Dm.reshape(-1))
+    n2 = L * L
+    aug = np.zeros((n2 + 1, n2 + 1), dtype=np.complex128)
+    aug[:n2, :n2] = M
+    aug[:n2, n2] = G.reshape(-1)
+    E = sla.expm(aug * t)
+    v0 = c_initial(occ).reshape(-1)
+    v = E[:n2, :n2] @ v0 + E[:n2, n2]
+    return v.reshape(L, L)

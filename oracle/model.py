@@ -146,3 +146,23 @@ def trotter_layers(order, dt):
     if order == 2:
         return [(1, dt / 2), (0, dt), (1, dt / 2)]
     raise ValueError("order must be 1 or 2")
+
+
+def channel_jumps(channels):
+    """Local jump list (site, 2x2 operator, rate) of a channel list (kind, site, rate).
+
+    kind "source" -> s+, "sink" -> s- (Jordan-Wigner strings dropped; they cancel in L rho L^+
+    for states block-diagonal in the particle number), "dephasing" -> n = s+ s-.
+    """
+    ops = {"source": SP, "sink": SM, "dephasing": SP @ SM}
+    return [(int(k), ops[kind].copy(), float(g)) for kind, k, g in channels]
+
+
+def two_sources(L, gamma=0.5):
+    """Alternative driving of Sec. 2.1: sources c_1^+ and c_N^+."""
+    return [("source", 0, gamma), ("source", L - 1, gamma)]
+
+
+def source_sink_dephasing(L, gamma=0.5, gamma_phi=0.2):
+    """Source c_1^+, sink c_N and dephasing c_i^+ c_i on every site (Sec. 2.1)."""
+    return [("source", 0, gamma), ("sink", L - 1, gamma)] + [("dephasing", i, gamma_phi) for i in range(L)]

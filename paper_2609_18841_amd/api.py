@@ -63,6 +63,17 @@ class Model:
         h = -J * (np.kron(sp, sm) + np.kron(sm, sp))
         return Model(L, [h] * (L - 1), [(0, sp, gamma), (L - 1, sm, gamma)])
 
+    @staticmethod
+    def channels(L, channels, J=1.0):
+        """Hopping chain of Sec. 2.1 with a list of (kind, site, rate) channels: kind "source"
+        (s+), "sink" (s-) or "dephasing" (n = s+ s-), e.g. the alternative drives the section
+        mentions (two sources; dephasing on every site)."""
+        sp = np.array([[0, 0], [1, 0]], dtype=np.complex128)
+        sm = sp.T.copy()
+        ops = {"source": sp, "sink": sm, "dephasing": sp @ sm}
+        h = -J * (np.kron(sp, sm) + np.kron(sm, sp))
+        return Model(L, [h] * (L - 1), [(int(k), ops[kind], float(g)) for kind, k, g in channels])
+
     def struct(self):
         m = _lib.TnModel()
         m.L = self.L

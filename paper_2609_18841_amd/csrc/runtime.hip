@@ -18,6 +18,7 @@
 #define TN_KIND_MPS 0
 #define TN_KIND_MPDO 1
 #define TN_KIND_PURIFIED 2
+#define TN_MAX_JUMPS 256  // as in the public header
 
 typedef struct tn_model {
     int L;
@@ -134,10 +135,10 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.off_rnd = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 2 * 8);
     ly.off_vals = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 8);
     ly.off_nrm = o; o = al(o + (size_t)B * 8);
-    ly.off_jsite = o; o = al(o + 16 * 4);
-    ly.off_jop = o; o = al(o + 16 * 4 * 16);
-    ly.off_jLdL = o; o = al(o + 16 * 4 * 16);
-    ly.off_gam = o; o = al(o + 16 * 8);
+    ly.off_jsite = o; o = al(o + (size_t)TN_MAX_JUMPS * 4);
+    ly.off_jop = o; o = al(o + (size_t)TN_MAX_JUMPS * 4 * 16);
+    ly.off_jLdL = o; o = al(o + (size_t)TN_MAX_JUMPS * 4 * 16);
+    ly.off_gam = o; o = al(o + (size_t)TN_MAX_JUMPS * 8);
     ly.off_ceach = o; o = al(o + (size_t)B * L * L * 16);
     ly.off_cmean = o; o = al(o + (size_t)L * L * 16);
     ly.off_cvar = o; o = al(o + (size_t)L * L * 8);
@@ -202,7 +203,7 @@ static bool model_ok(const tn_model* m, std::string& why) {
     if (m->L < 2) { why = "L must be >= 2"; return false; }
     if (m->d != 2) { why = "local dimension d must be 2"; return false; }
     if (!m->h_bond) { why = "h_bond is null"; return false; }
-    if (m->n_jumps < 0 || m->n_jumps > 8) { why = "n_jumps must be in 0..8"; return false; }
+    if (m->n_jumps < 0 || m->n_jumps > TN_MAX_JUMPS) { why = "n_jumps must be in 0..256"; return false; }
     if (m->n_jumps > 0 && (!m->jump_site || !m->jump_op || !m->gamma)) { why = "jump arrays are null"; return false; }
     for (int q = 0; q < m->n_jumps; ++q) {
         if (m->jump_site[q] < 0 || m->jump_site[q] >= m->L) { why = "jump site out of range"; return false; }
@@ -219,7 +220,7 @@ extern "C" size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int c
     int chunk = chunk_items > 0 ? chunk_items : default_chunk(L, batch, chi_max, dmax);
     int nbm = default_nbm(batch, L, chi_max);
     Layout ly;
-    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, 8, log_capacity(dmax * chi_max));
+    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, TN_MAX_JUMPS, log_capacity(dmax * chi_max));
     return ly.total;
 }
 
@@ -311,7 +312,7 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
     s->logcap = log_capacity(s->nmax);
     s->gstride = 256;
     s->nbmax = (L - 1 + 1) / 2;
-    compute_layout(s->lay, kind, L, batch, chi_max, s->dmax, precision, s->chunk, s->nbm, 8, s->logcap);
+    compute_layout(s->lay, kind, L, batch, chi_max, s->dmax, precision, s->chunk, s->nbm, TN_MAX_JUMPS, s->logcap);
     if (arena_bytes < s->lay.total) {
         size_t need = s->lay.total;
         delete s;

@@ -51,3 +51,18 @@ def test_host_gate_rejects_bad_bond():
     m = api.Model.free_fermion(4)
     with pytest.raises(api.TnError):
         api.tn_gate(api.KIND_MPS, m, 3, 0.1)
+
+
+@pytest.mark.parametrize("which", ["two_sources", "dephasing"])
+def test_host_gates_match_oracle_for_other_channel_sets(which):
+    """Alternative jump sets of Sec. 2.1 (two sources; dephasing on every site with source and
+    sink): the host gate builder agrees with the oracle's gates."""
+    L, tau = 6, 0.05
+    ch = M.two_sources(L, 0.5) if which == "two_sources" else M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    m = api.Model.channels(L, ch)
+    for b in range(L - 1):
+        g = api.tn_gate(api.KIND_MPS, m, b, tau)
+        assert np.max(np.abs(g - M.gate_heff(mdl, b, tau))) < 1e-14
+        G = api.tn_gate(api.KIND_MPDO, m, b, tau)
+        assert np.max(np.abs(G - M.gate_liouville(mdl, b, tau))) < 1e-14
