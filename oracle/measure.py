@@ -150,3 +150,18 @@ def jump_expectations(state, ops):
         O = _embed(Lop.conj().T @ Lop, B.shape[1])
         vals.append(float(np.real(np.sum(transfer_left(E[site], B, O) * R[site + 1]))))
     return nrm, vals
+
+
+def local_expectations(state, ops):
+    """(<psi|psi>_stored, [<psi|O_k|psi>_stored]) for single-site operators ops=[(site, O)], complex.
+
+    The shifted jump operators of Sec. 4.1 and 4.2 need <L_k> itself (not only <L_k^+ L_k>);
+    ratios to the norm give the expectation in the normalized state.
+    """
+    E, R = _envs(state)
+    nrm = float(np.real(E[state.L][0, 0]))
+    vals = []
+    for site, O in ops:
+        B = state.tensors[site]
+        vals.append(complex(np.sum(transfer_left(E[site], B, _embed(O, B.shape[1])) * R[site + 1])))
+    return nrm, vals

@@ -139,7 +139,8 @@ def trotter_layers(order, dt):
     """Sequence of (parity, time fraction) applied to the state, first element first.
 
     Sec. 2.3: first order e^{-iH_e dt} e^{-iH_o dt} acts with the odd bonds first;
-    second order e^{-iH_e dt/2} e^{-iH_o dt} e^{-iH_e dt/2}.  Reading C13.
+    second order e^{-iH_e dt/2} e^{-iH_o dt} e^{-iH_e dt/2}.  Parity 0 holds the bonds
+    (0,1), (2,3), ... (0-based), the paper's odd bonds.
     """
     if order == 1:
         return [(0, dt), (1, dt)]

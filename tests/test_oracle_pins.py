@@ -17,7 +17,8 @@ NEEL4 = [1, 0, 1, 0]
 @pytest.mark.parametrize("occ", [[0, 0, 0, 0], NEEL4, [1, 0, 1, 0, 1]])
 @pytest.mark.parametrize("t", [0.7, 1.3])
 def test_closed_form_matches_exact_lindblad(occ, t):
-    """eq. (SoleqCorr) with K read as in C1 equals exact integration of eq. (Lindblad)."""
+    """eq. (SoleqCorr), with the second edge term of K read as delta_iN delta_jN, equals exact
+    integration of eq. (Lindblad)."""
     L = len(occ)
     rho = ed.evolve_rho(occ, t, J=1.0, gamma=0.5, sink_string=True)
     C_ed = ed.corr_from_rho(rho, L)
@@ -27,7 +28,7 @@ def test_closed_form_matches_exact_lindblad(occ, t):
 
 
 def test_sink_string_does_not_change_correlations():
-    """Reading C3: dropping the Jordan-Wigner string of L2 leaves C(t) unchanged."""
+    """Dropping the Jordan-Wigner string of L2 = c_N in the jump leaves C(t) unchanged."""
     occ = [1, 0, 1, 0]
     a = ed.corr_from_rho(ed.evolve_rho(occ, 1.1, sink_string=True), 4)
     b = ed.corr_from_rho(ed.evolve_rho(occ, 1.1, sink_string=False), 4)
@@ -68,7 +69,7 @@ def test_special_case_no_hopping():
 
 
 def test_bond_liouvillians_sum_to_full_generator():
-    """Reading C2: sum_b of the two-site Liouvillians (local index m = n*2+n') is the
+    """With row-major vectorization (A rho B -> A (x) B^T), sum_b of the two-site Liouvillians (local index m = n*2+n') is the
     vectorized generator of eq. (Lindblad), built independently from operator matrices."""
     for L in (2, 3):
         mdl = M.Model(L, J=1.0, gamma=0.5)
@@ -415,3 +416,164 @@ def test_tebd_with_dephasing_matches_dense_trotter_and_exact():
         assert abs(tr - 1) < 1e-12
         errs.append(np.max(np.abs(C - exact.c_exact_channels(T, occ, ch))))
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+# ------------------------------------------------------------------ shifted jump operators
+def _site_op_dense(O, site, L):
+    return np.kron(np.kron(np.eye(2 ** site), O), np.eye(2 ** (L - site - 1)))
+
+
+def _random_state(L, seed=5):
+    import tn_inputs
+    tensors, lams, _ = tn_inputs.random_isometric_mps(seed, L, 8)
+    return tebd.TNState(tensors, lams)
+
+
+def _dense_shift_terms(psi, jumps, L):
+    """Normalized <L_k> and shifted rates <L^+L> - |<L>|^2, from dense operators."""
+    psi = psi / np.linalg.norm(psi)
+    ls, rates = [], []
+    for site, op, g in jumps:
+        Ld = _site_op_dense(op, site, L)
+        l = np.vdot(psi, Ld @ psi)
+        ls.append(l)
+        rates.append(g * (np.vdot(Ld @ psi, Ld @ psi).real - abs(l) ** 2))
+    return ls, rates
+
+
+def test_shifted_qt_jump_is_orthogonal_to_the_state():
+    """Sec. 4.1: with Delta_k = -<L_k> the jumped state (L_k - <L_k>) psi is orthogonal to psi,
+    and jump k is chosen with probability dt gamma_k (<L_k^+ L_k> - |<L_k>|^2)."""
+    L, dt = 6, 0.05
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    st0 = _random_state(L)
+    psi0 = tebd.to_dense(st0)
+    ls, rates = _dense_shift_terms(psi0, mdl.jumps, L)
+    assert min(abs(l) for l in ls) > 1e-3  # every shift is non-trivial on this state
+    edges = np.concatenate([[0.0], np.cumsum(rates) * dt])
+    for k in range(len(mdl.jumps)):
+        st = st0.copy()
+        u = 0.5 * (edges[k] + edges[k + 1])
+        assert stochastic.qt_jump_shifted(st, mdl.jumps, dt, u) == k
+        psi1 = tebd.to_dense(st)
+        assert abs(np.linalg.norm(psi1) - 1) < 1e-12
+        assert abs(np.vdot(psi0, psi1)) / np.linalg.norm(psi0) < 1e-12
+        site, op, g = mdl.jumps[k]
+        ref = _site_op_dense(op, site, L) @ psi0 - ls[k] * psi0
+        ref /= np.linalg.norm(ref)
+        assert abs(abs(np.vdot(ref, psi1)) - 1) < 1e-12
+    st = st0.copy()
+    assert stochastic.qt_jump_shifted(st, mdl.jumps, dt, edges[-1] + 1e-9) == -1
+
+
+def test_shifted_qt_norm_loss_equals_shifted_rates():
+    """Sec. 4.1: the no-jump evolution with the shifted h^eff loses norm
+    dt sum_k gamma_k (<L_k^+ L_k> - |<L_k>|^2) + O(dt^2); the unshifted loss differs by
+    dt sum_k gamma_k |<L_k>|^2, so a wrong drift factor fails this."""
+    L = 6
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)
+    st0 = _random_state(L)
+    ls, rates = _dense_shift_terms(tebd.to_dense(st0), mdl.jumps, L)
+    res = []
+    for dt in (0.01, 0.005):
+        st = st0.copy()
+        assert stochastic.qt_step_shifted(st, mdl.jumps, dt, 0.999999, fn, 64, 0.0) == -1
+        loss = 1 - np.linalg.norm(tebd.to_dense(st)) ** 2
+        res.append(loss - dt * sum(rates))
+        shift_part = dt * sum(g * abs(l) ** 2 for (s, o, g), l in zip(mdl.jumps, ls))
+        assert abs(res[-1]) < 0.1 * shift_part
+    assert abs(res[1]) < 0.35 * abs(res[0])  # O(dt^2)
+
+
+@pytest.mark.parametrize("shifted", [True, False])
+def test_shifted_qsd_norm_change_has_no_sqrt_dt_term(shifted):
+    """Sec. 4.2: with A_k = sqrt(gamma_k)(L_k - <L_k>) and binary noise the one-step change of
+    <psi|psi> is sum_{k != k'} eta_k eta_k' <A_k^+ A_k'> dt up to O(dt^{3/2}) for the linear step
+    psi + (sum eta_k A_k sqrt(dt) + B dt) psi.  The product form applied here, one factor per
+    channel in order, adds sum_{k<k'} eta_k eta_k' 2 Re<A_k' A_k> dt (zero on average).  Without
+    the shift a term ~ sqrt(dt) remains (checked as the contrast)."""
+    L = 6
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)
+    st0 = _random_state(L)
+    psi0 = tebd.to_dense(st0)
+    n0 = np.vdot(psi0, psi0).real
+    ls, _ = _dense_shift_terms(psi0, mdl.jumps, L)
+    u = np.random.default_rng(3).random(len(mdl.jumps))
+    eta = np.where(u < 0.5, -1.0, 1.0)
+    ph = psi0 / np.sqrt(n0)
+    Aop = [np.sqrt(g) * (_site_op_dense(op, s, L) - l * np.eye(2 ** L)) for (s, op, g), l in zip(mdl.jumps, ls)]
+    A = [a @ ph for a in Aop]
+    K = len(A)
+    cross = sum(eta[k] * eta[q] * np.vdot(A[k], A[q]) for k in range(K) for q in range(K) if k != q).real
+    cross += sum(2 * eta[k] * eta[q] * np.vdot(ph, Aop[q] @ A[k]).real for k in range(K) for q in range(k + 1, K))
+    res = []
+    for dt in (4e-4, 1e-4):
+        st = st0.copy()
+        step = stochastic.qsd_step_shifted if shifted else stochastic.qsd_step
+        step(st, mdl.jumps, dt, u, fn, 64, 0.0, noise_kind="binary")
+        n1 = np.linalg.norm(tebd.to_dense(st)) ** 2
+        res.append(n1 / n0 - 1 - cross * dt)
+    if shifted:
+        assert abs(res[1]) < 0.2 * abs(res[0])  # dt^{3/2} or faster: ratio <= 1/8
+        assert abs(res[0]) < 0.1 * abs(cross) * 4e-4
+    else:
+        assert 0.4 < abs(res[1]) / abs(res[0]) < 0.6  # the sqrt(dt) term
+
+
+def _traj_channels(kind, ntraj, L, T, dt, seed, ch, shifted):
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    occ = [1, 0] * (L // 2)
+    cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = M.gate_heff(mdl, b, tau)
+        return cache[(b, tau)]
+    nsteps = int(round(T / dt))
+    rng = np.random.default_rng(seed)
+    Cs, norms = [], []
+    for _ in range(ntraj):
+        st = tebd.product_state(occ, "mps")
+        if kind == "qt":
+            us = rng.random(nsteps)
+            step = stochastic.qt_step_shifted if shifted else (
+                lambda s, j, d, uu, f, c, e: stochastic.qt_step(s, mdl, j, d, uu, f, c, e))
+            for k in range(nsteps):
+                step(st, mdl.jumps, dt, us[k], fn, 32, 1e-12)
+            C, n2 = measure.corr_mps(st, normalize=True)
+        else:
+            rn = rng.standard_normal((nsteps, 2 * len(mdl.jumps)))
+            step = stochastic.qsd_step_shifted if shifted else stochastic.qsd_step
+            for k in range(nsteps):
+                step(st, mdl.jumps, dt, rn[k], fn, 32, 1e-12)
+            C, n2 = measure.corr_mps(st, normalize=False)
+            norms.append(n2)
+        Cs.append(C)
+    return np.array(Cs), np.array(norms)
+
+
+@pytest.mark.parametrize("kind", ["qt", "qsd"])
+def test_shifted_trajectory_average_matches_exact(kind):
+    """Any shift leaves the average dynamics equal to eq. (Lindblad): shifted QT and QSD
+    ensembles with dephasing (where <L_k> = <n_k> is not zero) match the exact C(t) within
+    eq. (ErrorCLT); the shifted QSD norm fluctuates less than the unshifted one (Sec. 4.2)."""
+    L, T, dt, ntraj = 4, 0.6, 0.01, 120
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    Cs, norms = _traj_channels(kind, ntraj, L, T, dt, 21, ch, True)
+    Cex = exact.c_exact_channels(T, [1, 0] * (L // 2), ch)
+    for part in (np.real, np.imag):
+        v = part(Cs[:, np.arange(L - 1), np.arange(1, L)])
+        mean, err = v.mean(0), v.std(0, ddof=1) / np.sqrt(ntraj)
+        assert np.all(np.abs(mean - part(Cex[np.arange(L - 1), np.arange(1, L)])) < 4 * err + 0.02)
+    n = np.real(np.einsum("tii->ti", Cs))
+    mean, err = n.mean(0), n.std(0, ddof=1) / np.sqrt(ntraj)
+    assert np.all(np.abs(mean - np.real(np.diag(Cex))) < 4 * err + 0.02)
+    if kind == "qsd":
+        _, norms_u = _traj_channels(kind, ntraj, L, T, dt, 21, ch, False)
+        assert abs(norms.mean() - 1) < 4 * norms.std(ddof=1) / np.sqrt(ntraj) + 0.02
+        assert norms.std() < 0.5 * norms_u.std()
