@@ -54,6 +54,8 @@ extern "C" {
 #define TN_MODE_QT    0  /* quantum-trajectory jumps, Sec. 4.1 */
 #define TN_MODE_QSD   1  /* quantum-state-diffusion noise, Sec. 4.2 */
 #define TN_MODE_KRAUS 2  /* Kraus-index compression of the purified form, Sec. 3.2 */
+#define TN_MODE_QT_SHIFT  3  /* QT with shifted jump operators L_k - <L_k>, Sec. 4.1 */
+#define TN_MODE_QSD_SHIFT 4  /* QSD with A_k = sqrt(gamma_k)(L_k - <L_k>) and the matching B, Sec. 4.2 */
 
 #define TN_NOISE_GAUSS  0  /* dW = sqrt(dt) (x + i y)/sqrt(2), x, y ~ N(0,1) */
 #define TN_NOISE_BINARY 1  /* dW = eta sqrt(dt), eta = -1 if u < 1/2 else +1 (the paper's choice) */
@@ -112,7 +114,17 @@ int tebd_step(void* s, double dt, int order, int n_steps, const unsigned char* m
  * TN_MODE_QSD (MPS): psi <- prod_k (1 + dW_k sqrt(gamma_k) L_k) psi (Sec. 4.2), no
  *   renormalization.  rnd = B*n_jumps*2 normals (GAUSS) or B*n_jumps uniforms (BINARY).
  * TN_MODE_KRAUS (PURIFIED): on each jump site, rho -> rho + gamma dt L rho L^+ then the
- *   Kraus index is compressed back to chi_k_max (eq. MatrixR, eq. NewPurified); rnd NULL. */
+ *   Kraus index is compressed back to chi_k_max (eq. MatrixR, eq. NewPurified); rnd NULL.
+ * Shifted modes, with l_k = <psi|L_k|psi>/<psi|psi> of the state on entry (every l_k of a call
+ * is taken before any of its factors is applied):
+ * TN_MODE_QT_SHIFT (MPS): as TN_MODE_QT with Delta_k = -l_k: rates gamma_k dt (<L_k^+L_k> -
+ *   |l_k|^2), the jumped state is (L_k - l_k) psi; without a jump each channel's factor
+ *   1 + dt gamma_k (conj(l_k) L_k - |l_k|^2/2), the state-dependent single-site part of the
+ *   shifted h^eff to first order, is applied in channel order (the caller then runs the
+ *   h^eff Trotter step under mask_out, as for TN_MODE_QT).
+ * TN_MODE_QSD_SHIFT (MPS): per channel in channel order,
+ *   psi <- (1 + dW_k sqrt(gamma_k)(L_k - l_k)) (1 + dt gamma_k (conj(l_k) L_k - |l_k|^2/2)) psi;
+ *   same rnd layout as TN_MODE_QSD. */
 int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
                 int* jumped_out, unsigned char* mask_out);
 

@@ -11,7 +11,7 @@ from . import _lib
 
 KIND_MPS, KIND_MPDO, KIND_PURIFIED = 0, 1, 2
 FP64, SPLIT = 0, 1
-MODE_QT, MODE_QSD, MODE_KRAUS = 0, 1, 2
+MODE_QT, MODE_QSD, MODE_KRAUS, MODE_QT_SHIFT, MODE_QSD_SHIFT = 0, 1, 2, 3, 4
 NOISE_GAUSS, NOISE_BINARY = 0, 1
 K_THETA, K_GRAM, K_HETRD, K_STEQR, K_VECS, K_SPLIT, K_MEASURE, K_JUMPS = range(8)
 K_NAMES = ["theta", "gram", "hetrd", "steqr", "vecs", "split", "measure", "jumps"]
@@ -147,6 +147,11 @@ class State:
 
     def apply_jumps(self, mode, dt, rnd=None, noise_kind=NOISE_GAUSS):
         r = None if rnd is None else np.ascontiguousarray(np.asarray(rnd, dtype=np.float64))
+        need = {MODE_QT: self.B, MODE_QT_SHIFT: self.B}.get(mode)
+        if mode in (MODE_QSD, MODE_QSD_SHIFT):
+            need = self.B * len(self.model.gam) * (2 if noise_kind == NOISE_GAUSS else 1)
+        if need is not None and r is not None and r.size < need:
+            raise ValueError(f"rnd holds {r.size} numbers, mode {mode} reads {need}")
         jumped = np.zeros(self.B, dtype=np.int32)
         mask = np.zeros(self.B, dtype=np.uint8)
         _check(self.lib.apply_jumps(self.h, mode, float(dt), _dp(r), noise_kind, _ip(jumped), _ubp(mask)))

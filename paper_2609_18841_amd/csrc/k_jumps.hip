@@ -1,6 +1,7 @@
 // Dissipative part of a time step (gfx950).
 //   quantum trajectories  (Sec. 4.1): jump choice from FP64 rates and uniforms, L_k applied locally;
 //   quantum state diffusion (Sec. 4.2): local factors 1 + dW_k sqrt(gamma_k) L_k, linear unravelling;
+//   both optionally with the shifted operators L_k - <L_k> and their drift (Sec. 4.1, 4.2);
 //   Kraus compression of the locally purified form (Sec. 3.2): new Kraus columns from the
 //   2chi_k x 2chi_k Gram matrix of M = [A | sqrt(gamma dt) L A], weighted by the left bond
 //   weights of the site (its environment in the Hastings form).
@@ -28,53 +29,84 @@ __device__ void apply_local(const DevState& s, int b, int site, double2 o00, dou
     }
 }
 
-// one block per instance of the chunk: decide and apply the jump
+// one block per instance of the chunk: decide and apply the jump.
+// Shifted operators (Sec. 4.1, lvals != null, l_k = lvals/nrm the normalized <L_k>): rates
+// gamma_k dt (<L_k^+L_k> - |l_k|^2), a jump applies L_k - l_k, and without a jump every channel's
+// factor 1 + dt gamma_k (conj(l_k) L_k - |l_k|^2/2) (the state-dependent single-site part of the
+// shifted h^eff, first order) is applied in channel order before the h^eff Trotter step.
 template <class T>
 __global__ void k_qt_apply(DevState s, int b0, double dt, int njump, const int* jsite, const double2* jop,
-                           const double* gam, const double* vals, const double* nrm, const double* rnd,
-                           int* jumped, unsigned char* mask) {
+                           const double* gam, const double* vals, const double2* lvals, const double* nrm,
+                           const double* rnd, int* jumped, unsigned char* mask) {
     const int bi = blockIdx.x, b = b0 + bi;
     __shared__ int sk;
+    const double nr = nrm[bi];
     if (threadIdx.x == 0) {
-        const double nr = nrm[bi];
         const double u = rnd[b];
         double cum = 0.0;
         int k = -1;
         for (int q = 0; q < njump; ++q) {
-            cum += gam[q] * dt * vals[(size_t)bi * njump + q] / nr;
+            double m = vals[(size_t)bi * njump + q] / nr;
+            if (lvals) {
+                const double2 l = cscale(lvals[(size_t)bi * njump + q], 1.0 / nr);
+                m -= l.x * l.x + l.y * l.y;
+            }
+            cum += gam[q] * dt * m;
             if (u < cum) { k = q; break; }
         }
         sk = k;
         jumped[b] = k;
         mask[b] = (k >= 0) ? 1 : 0;
-        // normalized state afterwards: jumped -> norm^2 = <L^+L>, else <B|B>
-        double n2 = (k >= 0) ? vals[(size_t)bi * njump + k] : nr;
+        // normalized state afterwards: jumped -> norm^2 = <L^+L> (shifted: nrm (m - |l|^2)), else <B|B>
+        double n2 = nr;
+        if (k >= 0) {
+            n2 = vals[(size_t)bi * njump + k];
+            if (lvals) {
+                const double2 l = cscale(lvals[(size_t)bi * njump + k], 1.0 / nr);
+                n2 = nr * (n2 / nr - (l.x * l.x + l.y * l.y));
+            }
+        }
         s.lognorm[b] = -0.5 * log(n2);
     }
     __syncthreads();
     const int k = sk;
     if (k >= 0) {
         const double2* o = jop + 4 * k;
-        apply_local<T>(s, b, jsite[k], o[0], o[1], o[2], o[3]);
+        double2 l = mk(0.0, 0.0);
+        if (lvals) l = cscale(lvals[(size_t)bi * njump + k], 1.0 / nr);
+        apply_local<T>(s, b, jsite[k], csub(o[0], l), o[1], o[2], csub(o[3], l));
+    } else if (lvals) {
+        for (int q = 0; q < njump; ++q) {
+            const double2* o = jop + 4 * q;
+            const double2 l = cscale(lvals[(size_t)bi * njump + q], 1.0 / nr);
+            const double c = dt * gam[q], h = 0.5 * c * (l.x * l.x + l.y * l.y);
+            const double2 cl = cscale(cconj(l), c);
+            apply_local<T>(s, b, jsite[q], cadd(mk(1.0 - h, 0.0), cmul(cl, o[0])), cmul(cl, o[1]), cmul(cl, o[2]),
+                           cadd(mk(1.0 - h, 0.0), cmul(cl, o[3])));
+            __syncthreads();
+        }
     }
 }
 
 void launch_qt_apply(int prec, const DevState& s, int b0, int nbm, double dt, int njump, const int* jsite,
-                     const double2* jop, const double* gam, const double* vals, const double* nrm,
-                     const double* rnd, int* jumped, unsigned char* mask, hipStream_t st) {
+                     const double2* jop, const double* gam, const double* vals, const double2* lvals,
+                     const double* nrm, const double* rnd, int* jumped, unsigned char* mask, hipStream_t st) {
     if (prec == 0)
         hipLaunchKernelGGL(k_qt_apply<double2>, dim3(nbm), dim3(256), 0, st, s, b0, dt, njump, jsite, jop, gam, vals,
-                           nrm, rnd, jumped, mask);
+                           lvals, nrm, rnd, jumped, mask);
     else
         hipLaunchKernelGGL(k_qt_apply<float2>, dim3(nbm), dim3(256), 0, st, s, b0, dt, njump, jsite, jop, gam, vals,
-                           nrm, rnd, jumped, mask);
+                           lvals, nrm, rnd, jumped, mask);
 }
 
-// one block per (instance, jump): psi <- (1 + dW sqrt(gamma) L) psi on the jump site
+// one block per (instance, jump): psi <- (1 + dW sqrt(gamma) L) psi on the jump site.
+// Shifted (Sec. 4.2, lvals != null): psi <- (1 + dW sqrt(gamma)(L - l)) (1 + dt gamma (conj(l) L - |l|^2/2)) psi
+// with l = lvals/nrm, the normalized <L> of the state before the step's first factor.
 template <class T>
-__global__ void k_qsd_apply(DevState s, double dt, int njump, int q, const int* jsite, const double2* jop,
-                            const double* gam, const double* rnd, int noise_kind) {
-    const int b = blockIdx.x;
+__global__ void k_qsd_apply(DevState s, int b0, double dt, int njump, int q, const int* jsite, const double2* jop,
+                            const double* gam, const double* rnd, int noise_kind, const double2* lvals,
+                            const double* nrm) {
+    const int bi = blockIdx.x, b = b0 + bi;
     double2 dW;
     if (noise_kind == 0) {
         double x = rnd[((size_t)b * njump + q) * 2 + 0], y = rnd[((size_t)b * njump + q) * 2 + 1];
@@ -91,19 +123,33 @@ __global__ void k_qsd_apply(DevState s, double dt, int njump, int q, const int* 
     double2 m01 = cmul(f, o[1]);
     double2 m10 = cmul(f, o[2]);
     double2 m11 = cadd(mk(1, 0), cmul(f, o[3]));
+    if (lvals) {
+        const double2 l = cscale(lvals[(size_t)bi * njump + q], 1.0 / nrm[bi]);
+        const double2 fl = cmul(f, l);
+        m00 = csub(m00, fl);
+        m11 = csub(m11, fl);
+        const double c = dt * gam[q], h = 0.5 * c * (l.x * l.x + l.y * l.y);
+        const double2 cl = cscale(cconj(l), c);
+        const double2 d00 = cadd(mk(1.0 - h, 0.0), cmul(cl, o[0])), d01 = cmul(cl, o[1]);
+        const double2 d10 = cmul(cl, o[2]), d11 = cadd(mk(1.0 - h, 0.0), cmul(cl, o[3]));
+        const double2 n00 = cadd(cmul(m00, d00), cmul(m01, d10)), n01 = cadd(cmul(m00, d01), cmul(m01, d11));
+        const double2 n10 = cadd(cmul(m10, d00), cmul(m11, d10)), n11 = cadd(cmul(m10, d01), cmul(m11, d11));
+        m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+    }
     apply_local<T>(s, b, jsite[q], m00, m01, m10, m11);
 }
 
-void launch_qsd_apply(int prec, const DevState& s, double dt, int njump, const int* jsite, const double2* jop,
-                      const double* gam, const double* rnd, int noise_kind, hipStream_t st) {
+void launch_qsd_apply(int prec, const DevState& s, int b0, int nbm, double dt, int njump, const int* jsite,
+                      const double2* jop, const double* gam, const double* rnd, int noise_kind, const double2* lvals,
+                      const double* nrm, hipStream_t st) {
     // one launch per jump: factors acting on the same site are applied in jump order
     for (int q = 0; q < njump; ++q) {
         if (prec == 0)
-            hipLaunchKernelGGL(k_qsd_apply<double2>, dim3(s.B), dim3(256), 0, st, s, dt, njump, q, jsite, jop, gam,
-                               rnd, noise_kind);
+            hipLaunchKernelGGL(k_qsd_apply<double2>, dim3(nbm), dim3(256), 0, st, s, b0, dt, njump, q, jsite, jop,
+                               gam, rnd, noise_kind, lvals, nrm);
         else
-            hipLaunchKernelGGL(k_qsd_apply<float2>, dim3(s.B), dim3(256), 0, st, s, dt, njump, q, jsite, jop, gam,
-                               rnd, noise_kind);
+            hipLaunchKernelGGL(k_qsd_apply<float2>, dim3(nbm), dim3(256), 0, st, s, b0, dt, njump, q, jsite, jop,
+                               gam, rnd, noise_kind, lvals, nrm);
     }
 }
 

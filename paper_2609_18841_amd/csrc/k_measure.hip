@@ -239,11 +239,14 @@ void launch_measure_mps(int prec, const DevState& s, const MeasWork& mw, hipStre
     else measure_mps_t<float2>(s, mw, st);
 }
 
-// ---------------------------------------------------------------- QT rates
-// closing of O = L^+L on site j: sum O[n'][n] sum_k <Y[(n,k)], W[(n',k)]>, Y = E_{j-1} B_j
+// ---------------------------------------------------------------- QT rates, shift means
+// closing of a local O on site j: <psi|O|psi> = sum O[n'][n] sum_k <Y[(n,k)], W[(n',k)]>, Y = E_{j-1} B_j
+// (row index n' = bra).  O = L^+L gives the rate numerator (real part to vals); O = L gives <L>
+// for the shifted jump operators (complex, to cvals when it is non-null).
 template <class T>
 __global__ __launch_bounds__(NT) void k_jump_dot(DevState s, MeasWork mw, int j, double2 o00, double2 o01,
-                                                  double2 o10, double2 o11, double* vals, int njump, int jk) {
+                                                  double2 o10, double2 o11, double* vals, double2* cvals, int njump,
+                                                  int jk) {
     __shared__ double2 red[NT];
     const int bi = blockIdx.x, b = mw.b0 + bi;
     SiteDims sd = site_dims(s, b, j);
@@ -270,13 +273,16 @@ __global__ __launch_bounds__(NT) void k_jump_dot(DevState s, MeasWork mw, int j,
         if (threadIdx.x < o) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) vals[(size_t)bi * njump + jk] = red[0].x;
+    if (threadIdx.x == 0) {
+        if (cvals) cvals[(size_t)bi * njump + jk] = red[0];
+        else vals[(size_t)bi * njump + jk] = red[0].x;
+    }
 }
 
 // E_j for all j are not stored; instead the left sweep stops at each jump site.
 template <class T>
 static void jump_expect_t(const DevState& s, const MeasWork& mw, int njump, const int* jsite,
-                          const double2* jLdL, double* vals, hipStream_t st) {
+                          const double2* jLdL, double* vals, const double2* jL, double2* lvals, hipStream_t st) {
     const int ch = (s.chi + 63) / 64, chd = (s.chi * s.dmax + 63) / 64;
     hipLaunchKernelGGL(k_meas_init<T>, dim3((mw.nbm + 63) / 64), dim3(64), 0, st, s, mw);
     for (int j = s.L - 1; j >= 0; --j) {
@@ -286,11 +292,18 @@ static void jump_expect_t(const DevState& s, const MeasWork& mw, int njump, cons
     for (int j = 0; j < s.L; ++j) {
         // Y = E_{j-1} B_j (slot 0 plays the role of the norm environment)
         hipLaunchKernelGGL(k_meas_y<T>, dim3(ch * chd, mw.nbm), dim3(NT), 0, st, s, mw, j, 0, chd);
+        bool have_w = false;
         for (int q = 0; q < njump; ++q) {
             if (jsite[q] != j) continue;
-            hipLaunchKernelGGL(k_meas_w<T>, dim3(chd * ch, mw.nbm), dim3(NT), 0, st, s, mw, j, ch);
+            if (!have_w) {  // W = conj(B_j) R_{j+1}, shared by every channel on this site
+                hipLaunchKernelGGL(k_meas_w<T>, dim3(chd * ch, mw.nbm), dim3(NT), 0, st, s, mw, j, ch);
+                have_w = true;
+            }
             hipLaunchKernelGGL(k_jump_dot<T>, dim3(mw.nbm), dim3(NT), 0, st, s, mw, j, jLdL[4 * q + 0],
-                               jLdL[4 * q + 1], jLdL[4 * q + 2], jLdL[4 * q + 3], vals, njump, q);
+                               jLdL[4 * q + 1], jLdL[4 * q + 2], jLdL[4 * q + 3], vals, (double2*)nullptr, njump, q);
+            if (jL)
+                hipLaunchKernelGGL(k_jump_dot<T>, dim3(mw.nbm), dim3(NT), 0, st, s, mw, j, jL[4 * q + 0],
+                                   jL[4 * q + 1], jL[4 * q + 2], jL[4 * q + 3], (double*)nullptr, lvals, njump, q);
         }
         // E_j = sum_p B^p+ Y^p  (slot nslot_x+1 with nslot_x = 0 -> E update only; the s+ slot writes X[j], unused)
         hipLaunchKernelGGL(k_meas_upd<T>, dim3(ch * ch, mw.nbm * 2), dim3(NT), 0, st, s, mw, j, 0, ch);
@@ -299,9 +312,9 @@ static void jump_expect_t(const DevState& s, const MeasWork& mw, int njump, cons
 }
 
 void launch_jump_expect(int prec, const DevState& s, const MeasWork& mw, int njump, const int* jsite,
-                        const double2* jLdL, double* vals, hipStream_t st) {
-    if (prec == 0) jump_expect_t<double2>(s, mw, njump, jsite, jLdL, vals, st);
-    else jump_expect_t<float2>(s, mw, njump, jsite, jLdL, vals, st);
+                        const double2* jLdL, double* vals, const double2* jL, double2* lvals, hipStream_t st) {
+    if (prec == 0) jump_expect_t<double2>(s, mw, njump, jsite, jLdL, vals, jL, lvals, st);
+    else jump_expect_t<float2>(s, mw, njump, jsite, jLdL, vals, jL, lvals, st);
 }
 
 // ---------------------------------------------------------------- MPDO (trace vectors)

@@ -47,16 +47,18 @@ struct MeasWork {
 void launch_measure_mps(int prec, const DevState& s, const MeasWork& mw, hipStream_t st);
 void launch_measure_mpdo(int prec, const DevState& s, const MeasWork& mw, hipStream_t st);
 // right/left norm environments only (QT rates): fills mw.R for all sites and returns per-instance
-// closings of the jump operators L^+L into vals[nbm * njump]
+// closings of the jump operators L^+L into vals[nbm * njump] (real parts) and, when jL is non-null,
+// of L itself into lvals[nbm * njump] (complex); jLdL, jL: host arrays, njump*4 row-major 2x2
 void launch_jump_expect(int prec, const DevState& s, const MeasWork& mw, int njump, const int* jsite,
-                        const double2* jLdL /* njump*4 */, double* vals, hipStream_t st);
+                        const double2* jLdL, double* vals, const double2* jL, double2* lvals, hipStream_t st);
 
-// dissipative kernels (k_jumps.hip)
+// dissipative kernels (k_jumps.hip); lvals == null: unshifted operators
 void launch_qt_apply(int prec, const DevState& s, int b0, int nbm, double dt, int njump, const int* jsite,
-                     const double2* jop, const double* gam, const double* vals, const double* nrm,
-                     const double* rnd, int* jumped, unsigned char* mask, hipStream_t st);
-void launch_qsd_apply(int prec, const DevState& s, double dt, int njump, const int* jsite, const double2* jop,
-                      const double* gam, const double* rnd, int noise_kind, hipStream_t st);
+                     const double2* jop, const double* gam, const double* vals, const double2* lvals,
+                     const double* nrm, const double* rnd, int* jumped, unsigned char* mask, hipStream_t st);
+void launch_qsd_apply(int prec, const DevState& s, int b0, int nbm, double dt, int njump, const int* jsite,
+                      const double2* jop, const double* gam, const double* rnd, int noise_kind, const double2* lvals,
+                      const double* nrm, hipStream_t st);
 // jsite, jop, gam: host arrays (passed to the kernel by value)
 void launch_kraus(int prec, const DevState& s, double dt, int njump, const int* jsite, const double2* jop,
                   const double* gam, int chik, hipStream_t st);

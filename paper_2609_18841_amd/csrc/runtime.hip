@@ -11,24 +11,10 @@
 #include <string>
 #include <vector>
 
+#include "tebd.h"
 #include "common.h"
 #include "host_gates.h"
 #include "launch.h"
-
-#define TN_KIND_MPS 0
-#define TN_KIND_MPDO 1
-#define TN_KIND_PURIFIED 2
-#define TN_MAX_JUMPS 256  // as in the public header
-
-typedef struct tn_model {
-    int L;
-    int d;
-    const double* h_bond;
-    int n_jumps;
-    const int* jump_site;
-    const double* jump_op;
-    const double* gamma;
-} tn_model;
 
 static thread_local std::string g_err;
 
@@ -63,7 +49,7 @@ void prof_end(Prof* p, int id, hipStream_t st) {
 // ------------------------------------------------------------------ state
 struct Layout {
     size_t off_tens, off_lam, off_dims, off_lognorm, off_trunc, off_dsite, off_mask, off_jumped, off_glog, off_gwt,
-        off_gates, off_rnd, off_vals, off_nrm, off_jsite, off_jop, off_jLdL, off_gam, off_ceach, off_cmean, off_cvar,
+        off_gates, off_rnd, off_vals, off_lval, off_nrm, off_jsite, off_jop, off_jLdL, off_gam, off_ceach, off_cmean, off_cvar,
         off_flags, off_ws;
     size_t ws_bytes, total;
     // workspace sub-layout (update)
@@ -134,6 +120,7 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.off_gates = o; o = al(o + (size_t)2 * (L - 1) * 256 * 16);
     ly.off_rnd = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 2 * 8);
     ly.off_vals = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 8);
+    ly.off_lval = o; o = al(o + (size_t)B * (njump > 0 ? njump : 1) * 16);
     ly.off_nrm = o; o = al(o + (size_t)B * 8);
     ly.off_jsite = o; o = al(o + (size_t)TN_MAX_JUMPS * 4);
     ly.off_jop = o; o = al(o + (size_t)TN_MAX_JUMPS * 4 * 16);
@@ -831,29 +818,40 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
     const int* jsite = at<int>(s, s->lay.off_jsite);
     const double2* jop = at<double2>(s, s->lay.off_jop);
     const double* gam = at<double>(s, s->lay.off_gam);
+    const bool qt = mode == TN_MODE_QT || mode == TN_MODE_QT_SHIFT;
+    const bool qsd = mode == TN_MODE_QSD || mode == TN_MODE_QSD_SHIFT;
+    const bool shifted = mode == TN_MODE_QT_SHIFT || mode == TN_MODE_QSD_SHIFT;
+    if (!qt && !qsd && mode != TN_MODE_KRAUS) return fail(TN_EINVAL, "unknown mode");
+    if (qt && s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QT jumps need kind MPS");
+    if (qsd && s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QSD noise needs kind MPS");
+    if ((qt || qsd) && !rnd) return fail(TN_EINVAL, "rnd is null");
+    if (qsd && noise_kind != 0 && noise_kind != 1) return fail(TN_EINVAL, "unknown noise kind");
+    if (mode == TN_MODE_KRAUS && s->kind != TN_KIND_PURIFIED)
+        return fail(TN_EINVAL, "Kraus compression needs kind PURIFIED");
     prof_begin(&s->prof, TN_K_JUMPS, s->stream);
-    if (mode == 0) {
-        if (s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QT jumps need kind MPS");
-        if (!rnd) return fail(TN_EINVAL, "rnd is null");
+    // host copies of L (row-major 2x2 per channel) and L^+L for the closing kernels
+    std::vector<double2> jl(4 * s->njump), jL(4 * s->njump);
+    for (int q = 0; q < s->njump; ++q) {
+        double2 o[4];
+        for (int e = 0; e < 4; ++e) o[e] = mk(s->model.jump_op[8 * q + 2 * e], s->model.jump_op[8 * q + 2 * e + 1]);
+        for (int e = 0; e < 4; ++e) jL[4 * q + e] = o[e];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) {
+                double2 acc = mk(0, 0);
+                for (int k = 0; k < 2; ++k) cfmac(acc, o[k * 2 + r], o[k * 2 + c]);
+                jl[4 * q + r * 2 + c] = acc;
+            }
+    }
+    double* vals = at<double>(s, s->lay.off_vals);
+    double2* lvals = shifted ? at<double2>(s, s->lay.off_lval) : nullptr;
+    if (qt) {
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, (size_t)s->B * 8, hipMemcpyHostToDevice, s->stream));
-        std::vector<double2> jl(4 * s->njump);
-        // L^+L on the host (the device copy is used by no kernel argument list here)
-        for (int q = 0; q < s->njump; ++q) {
-            double2 o[4];
-            for (int e = 0; e < 4; ++e) o[e] = mk(s->model.jump_op[8 * q + 2 * e], s->model.jump_op[8 * q + 2 * e + 1]);
-            for (int r = 0; r < 2; ++r)
-                for (int c = 0; c < 2; ++c) {
-                    double2 acc = mk(0, 0);
-                    for (int k = 0; k < 2; ++k) cfmac(acc, o[k * 2 + r], o[k * 2 + c]);
-                    jl[4 * q + r * 2 + c] = acc;
-                }
-        }
         for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
             int nbm = std::min(s->nbm, s->B - b0);
             MeasWork mw = meas_work(s, b0, nbm);
-            double* vals = at<double>(s, s->lay.off_vals);
-            launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals, s->stream);
-            launch_qt_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam, vals, mw.nrm,
+            launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals,
+                               shifted ? jL.data() : nullptr, lvals, s->stream);
+            launch_qt_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam, vals, lvals, mw.nrm,
                             at<double>(s, s->lay.off_rnd), at<int>(s, s->lay.off_jumped),
                             reinterpret_cast<unsigned char*>(s->arena + s->lay.off_mask), s->stream);
             HIPCHK(hipGetLastError());
@@ -863,17 +861,24 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
                                   s->stream));
         if (mask_out)
             HIPCHK(hipMemcpyAsync(mask_out, s->arena + s->lay.off_mask, (size_t)s->B, hipMemcpyDeviceToHost, s->stream));
-    } else if (mode == 1) {
-        if (s->kind != TN_KIND_MPS) return fail(TN_EINVAL, "QSD noise needs kind MPS");
-        if (!rnd) return fail(TN_EINVAL, "rnd is null");
-        if (noise_kind != 0 && noise_kind != 1) return fail(TN_EINVAL, "unknown noise kind");
+    } else if (qsd) {
         size_t n = (size_t)s->B * s->njump * (noise_kind == 0 ? 2 : 1);
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, n * 8, hipMemcpyHostToDevice, s->stream));
-        launch_qsd_apply(s->prec, ds, dt, s->njump, jsite, jop, gam, at<double>(s, s->lay.off_rnd), noise_kind,
-                         s->stream);
+        if (!shifted) {
+            launch_qsd_apply(s->prec, ds, 0, s->B, dt, s->njump, jsite, jop, gam, at<double>(s, s->lay.off_rnd),
+                             noise_kind, nullptr, nullptr, s->stream);
+        } else {
+            for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
+                int nbm = std::min(s->nbm, s->B - b0);
+                MeasWork mw = meas_work(s, b0, nbm);
+                launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals, jL.data(),
+                                   lvals, s->stream);
+                launch_qsd_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam,
+                                 at<double>(s, s->lay.off_rnd), noise_kind, lvals, mw.nrm, s->stream);
+            }
+        }
         HIPCHK(hipGetLastError());
-    } else if (mode == 2) {
-        if (s->kind != TN_KIND_PURIFIED) return fail(TN_EINVAL, "Kraus compression needs kind PURIFIED");
+    } else if (mode == TN_MODE_KRAUS) {
         std::vector<double2> hop(4 * s->njump);
         for (int q = 0; q < 4 * s->njump; ++q) hop[q] = mk(s->model.jump_op[2 * q], s->model.jump_op[2 * q + 1]);
         launch_kraus(s->prec, ds, dt, s->njump, s->model.jump_site.data(), hop.data(), s->model.gamma.data(), s->chik,

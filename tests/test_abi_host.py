@@ -66,3 +66,20 @@ def test_host_gates_match_oracle_for_other_channel_sets(which):
         assert np.max(np.abs(g - M.gate_heff(mdl, b, tau))) < 1e-14
         G = api.tn_gate(api.KIND_MPDO, m, b, tau)
         assert np.max(np.abs(G - M.gate_liouville(mdl, b, tau))) < 1e-14
+
+
+def test_binding_constants_match_header():
+    """Every #define of include/tebd.h that the binding mirrors has the header's value."""
+    import re
+    from paper_2609_18841_amd import api
+    hdr = open(os.path.join(ROOT, "include", "tebd.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (TN_\w+)\s+(-?\d+)", hdr)}
+    pairs = {"TN_KIND_MPS": api.KIND_MPS, "TN_KIND_MPDO": api.KIND_MPDO, "TN_KIND_PURIFIED": api.KIND_PURIFIED,
+             "TN_FP64": api.FP64, "TN_SPLIT": api.SPLIT, "TN_MODE_QT": api.MODE_QT, "TN_MODE_QSD": api.MODE_QSD,
+             "TN_MODE_KRAUS": api.MODE_KRAUS, "TN_MODE_QT_SHIFT": api.MODE_QT_SHIFT,
+             "TN_MODE_QSD_SHIFT": api.MODE_QSD_SHIFT, "TN_NOISE_GAUSS": api.NOISE_GAUSS,
+             "TN_NOISE_BINARY": api.NOISE_BINARY}
+    for name, val in pairs.items():
+        assert defs[name] == val, name
+    for i, k in enumerate(api.K_NAMES):
+        assert defs["TN_K_" + k.upper()] == i
