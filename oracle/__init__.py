@@ -21,6 +21,7 @@ ed         exact integration of the full Lindblad equation for small chains
 dense      exact Trotter products on the full state vector / density vector
 tebd       Hastings-form TEBD two-site update + layer schedule (Sec. 2.3, 3.1,
            3.2, 4)
+sweep      the paper's sequential mixed-canonical sweep (Sec. 2.3, eq. ShiftCenter)
 stochastic quantum-trajectory and quantum-state-diffusion steps (Sec. 4.1, 4.2)
 kraus      Kraus-index compression of the locally purified form (Sec. 3.2)
 measure    <c_i^+ c_j> by exact (gauge-independent) contraction

@@ -577,3 +577,82 @@ def test_shifted_trajectory_average_matches_exact(kind):
         _, norms_u = _traj_channels(kind, ntraj, L, T, dt, 21, ch, False)
         assert abs(norms.mean() - 1) < 4 * norms.std(ddof=1) / np.sqrt(ntraj) + 0.02
         assert norms.std() < 0.5 * norms_u.std()
+
+
+# ------------------------------------------------------------------ sequential sweep (Sec. 2.3)
+from oracle import sweep  # noqa: E402
+
+
+@pytest.mark.parametrize("kind,order", [("mps", 1), ("mps", 2), ("mpdo", 1), ("mpdo", 2)])
+def test_sweep_equals_dense_trotter_without_truncation(kind, order):
+    """The sequential sweep applies exactly the Trotter product of Sec. 2.3 (chi not binding),
+    with the dephasing channel set, so every gate of the chain is non-unitary."""
+    L = 6 if kind == "mps" else 5
+    occ = [1, 0, 1, 0, 1, 0][:L]
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    fn = (lambda b, tau: M.gate_heff(mdl, b, tau)) if kind == "mps" else _mpdo_gate_fn(mdl)
+    d = 2 if kind == "mps" else 4
+    st = tebd.product_state(occ, kind)
+    for _ in range(4):
+        sweep.sweep_trotter_step(st, fn, order, 0.1, chi_max=d ** L, cutoff=0.0)
+    v = dense.trotter_dense(dense.product_vector(occ, d, kind), fn, order, 0.1, 4)
+    assert np.max(np.abs(tebd.to_dense(st).reshape((d,) * L) - v)) < 1e-12
+
+
+def _gauge_r_defect(T):
+    """max |sum_p T^p T^p+ - 1| (eq. GaugeR) for T[a, p, c]."""
+    M2 = np.einsum("apc,bpc->ab", T, T.conj())
+    return np.max(np.abs(M2 - np.eye(T.shape[0])))
+
+
+def test_sweep_keeps_right_canonical_form_with_nonunitary_gates():
+    """After each step of the sweep every tensor but the centre (site 0) satisfies eq. GaugeR,
+    although the gates are not unitary; the layer-parallel form loses it on the same run."""
+    L = 6
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)
+    s1 = tebd.product_state([1, 0] * 3, "mps")
+    s2 = s1.copy()
+    for _ in range(6):
+        sweep.sweep_trotter_step(s1, fn, 1, 0.1, 64, 0.0)
+        tebd.trotter_step(s2, fn, 1, 0.1, 64, 0.0)
+        assert max(_gauge_r_defect(T) for T in s1.tensors[1:]) < 1e-12
+    assert max(_gauge_r_defect(T) for T in s2.tensors[1:]) > 1e-3
+
+
+def test_sweep_discarded_weight_is_hilbert_schmidt_error_at_binding_chi():
+    """With the centre inside the updated block, the SVD truncation of every update (gate or
+    centre shift) removes exactly its discarded weight from the whole state:
+    ||psi_full - psi_kept||^2 / ||psi_full||^2 = sum_{a>=k} S_a^2 / sum S_a^2 (eq.
+    HilbertSchmidtNorm), with non-unitary gates and chi binding."""
+    import tn_inputs
+    L, chi = 6, 3
+    tensors, lams, _ = tn_inputs.random_isometric_mps(9, L, 8)
+    st = tebd.TNState(tensors, lams)
+    ch = M.source_sink_dephasing(L, 0.5, 0.3)
+    mdl = M.Model(L, jumps=M.channel_jumps(ch))
+    layers = M.trotter_layers(1, 0.2)
+    nontrivial = 0
+    for b, li, right in sweep.sweep_schedule(L, 1):
+        G = None if li < 0 else M.gate_heff(mdl, b, layers[li][1])
+        psi = tebd.to_dense(st)
+        if G is not None:
+            psi = dense.apply_gate(psi.reshape((2,) * L), G, b).reshape(-1)
+        w = sweep.center_update(st, b, G, chi, 0.0, right)
+        err = np.linalg.norm(psi - tebd.to_dense(st)) ** 2 / np.linalg.norm(psi) ** 2
+        assert abs(err - w) < 1e-12 * max(1.0, w)
+        nontrivial += w > 1e-6
+    assert nontrivial >= 3
+
+
+def test_sweep_schedule_follows_the_paper_for_first_order():
+    """Sec. 2.3, written out for N = 6 from the paper's description: gate (1,2), shift the centre,
+    gate (3,4), shift, gate (5,6) -- the centre reaches the right edge -- then the even bonds in
+    reverse order, (4,5) then (2,3), each preceded by a centre shift to the left, and a last
+    shift back to the first site.  0-based bonds; -1 marks a centre shift."""
+    R, Lf = True, False
+    expect = [(0, 0, R), (1, -1, R), (2, 0, R), (3, -1, R), (4, 0, R),
+              (4, -1, Lf), (3, 1, Lf), (2, -1, Lf), (1, 1, Lf), (0, -1, Lf)]
+    assert sweep.sweep_schedule(6, 1) == expect
