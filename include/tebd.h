@@ -57,6 +57,9 @@ extern "C" {
 #define TN_MODE_QT_SHIFT  3  /* QT with shifted jump operators L_k - <L_k>, Sec. 4.1 */
 #define TN_MODE_QSD_SHIFT 4  /* QSD with A_k = sqrt(gamma_k)(L_k - <L_k>) and the matching B, Sec. 4.2 */
 
+#define TN_SCHED_LAYER 0  /* layer-parallel Hastings form: all bonds of a parity at once */
+#define TN_SCHED_SWEEP 1  /* the paper's sequential sweep with the orthogonality centre, Sec. 2.3 */
+
 #define TN_NOISE_GAUSS  0  /* dW = sqrt(dt) (x + i y)/sqrt(2), x, y ~ N(0,1) */
 #define TN_NOISE_BINARY 1  /* dW = eta sqrt(dt), eta = -1 if u < 1/2 else +1 (the paper's choice) */
 
@@ -189,6 +192,23 @@ int tn_tuning(void* s, int set_variant, int* variant_out, float* ms_out);
  * on = 0 switches replay off and releases the captured graphs; on = 1 (the default) allows it.
  * Returns TN_OK or TN_EINVAL (null handle). */
 int tn_graph_enable(void* s, int on);
+
+/* ---- Trotter schedule ----------------------------------------------------- */
+
+/* Selects how tebd_step applies a Trotter step (both give the same Trotter product, Sec. 2.3):
+ * TN_SCHED_LAYER (default): every bond of one parity of every instance is one independent
+ *   update (Hastings form, Lambda_{bond-1} as the left environment); exact canonical form is
+ *   kept for unitary gates.
+ * TN_SCHED_SWEEP: the paper's sequential sweep in the mixed decomposition (eq. MPSMixte):
+ *   each two-site SVD is taken on a block holding the orthogonality centre, without Lambda
+ *   weights, so the truncation is optimal for any gate; the centre moves by SVD shifts with
+ *   the identity gate (eq. ShiftCenter).  Passes alternate direction starting left to right;
+ *   before each gate the centre is shifted onto the bond; after the last pass it returns to
+ *   site 0, so between steps every tensor but site 0 is right-canonical (eq. GaugeR) and the
+ *   state has the same storage form under both schedules.  Parallel over instances only:
+ *   about 2(L-1) (order 1) or 4(L-1) (order 2) dependent launch sequences per step.
+ * Returns TN_OK or TN_EINVAL (null handle, unknown schedule). */
+int tn_schedule(void* s, int schedule);
 
 /* ---- kernel timing (HIP events on the library stream) -------------------- */
 #define TN_K_THETA   0  /* Theta formation + gate */

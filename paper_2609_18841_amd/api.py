@@ -13,6 +13,7 @@ KIND_MPS, KIND_MPDO, KIND_PURIFIED = 0, 1, 2
 FP64, SPLIT = 0, 1
 MODE_QT, MODE_QSD, MODE_KRAUS, MODE_QT_SHIFT, MODE_QSD_SHIFT = 0, 1, 2, 3, 4
 NOISE_GAUSS, NOISE_BINARY = 0, 1
+SCHED_LAYER, SCHED_SWEEP = 0, 1
 K_THETA, K_GRAM, K_HETRD, K_STEQR, K_VECS, K_SPLIT, K_MEASURE, K_JUMPS = range(8)
 K_NAMES = ["theta", "gram", "hetrd", "steqr", "vecs", "split", "measure", "jumps"]
 
@@ -220,6 +221,11 @@ class State:
     def graph_enable(self, on=True):
         """Allow (default) or forbid HIP-graph replay of unmasked Trotter steps."""
         _check(self.lib.tn_graph_enable(self.h, 1 if on else 0))
+
+    def schedule(self, sched):
+        """SCHED_LAYER (layer-parallel Hastings form) or SCHED_SWEEP (sequential sweep with the
+        orthogonality centre, Sec. 2.3) for the following tebd_step calls."""
+        _check(self.lib.tn_schedule(self.h, int(sched)))
 
     def prof_query(self, kid):
         ms = ctypes.c_double()

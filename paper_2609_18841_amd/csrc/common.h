@@ -109,6 +109,10 @@ struct DevWork {
     double2* Y;                  // items * ysz  Y = Theta~ V, column-major m x r (aliases the Gram slot)
     int ldy;                     // leading dimension of Y (>= mmax)
     size_t ysz;                  // elements per item
+    // sequential sweep (orthogonality centre inside the block): no Lambda_{bond-1} weights;
+    // rmove: the centre leaves on site bond+1 (B_bond left-isometric, B_{bond+1} = diag(Lambda) V^+);
+    // skip_gate: identity gate (centre shift)
+    int unitw = 0, rmove = 0, skip_gate = 0;
 };
 
 // item -> (instance, bond); returns false for masked items

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(NT) void k_gram(DevState s, DevWork w, int tiles_n)
     int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.n || tn * 64 >= d.n || tm < tn) return;  // lower block triangle only
     const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
-    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    const double* lamL = (d.bond > 0 && !w.unitw) ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
     const int n = d.n, dl = d.dl;
     double2* G = w.gram + (size_t)blockIdx.y * w.nmax * w.nmax;
     block_gemm<double2, false, true, 8>(
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(NT) void k_qr_wide(DevState s, DevWork w) {
     if (!(d.m < d.n)) return;
     const int m = d.m, n = d.n, tid = threadIdx.x;
     const double2* th = reinterpret_cast<const double2*>(w.theta) + (size_t)j * w.theta_stride;
-    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    const double* lamL = (d.bond > 0 && !w.unitw) ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
     double2* A = w.qra + (size_t)j * w.nmax * w.nmax;   // n x m, row-major, ld = m
     double2* qt = w.qtau + (size_t)j * w.nmax;
     // A[r][c] = conj(Theta[c][r]), Theta = Lambda_left Theta~
@@ -1470,6 +1470,23 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     T* Bl = site_ptr<T>(s, d.b, d.bond);
     const int n = d.n, chi = w.vld;
     const R inv = (R)(1.0 / sv);
+    if (w.rmove) {
+        // centre moves right: B_bond = Theta~ V diag(1/S) (left isometry), B_{bond+1} <- diag(Lambda) V^+
+        const double* lam = lam_ptr(s, d.b, d.bond);
+        if (blockIdx.x == 0) {
+            T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+            for (int e = threadIdx.x; e < k * n; e += NT) Br[e] = cscale(Br[e], (R)lam[e / n]);
+        }
+        block_gemm<T, true, true, 8>(
+            d.m, k, n, tm * 64, tn * 64,
+            [&](int r, int q) { return th[(size_t)r * n + q]; },
+            [&](int q, int c) { return cconv<T>(V[(size_t)q * chi + c]); },
+            [&](int r, int c, T v) {
+                const double sc = lam[c] > 0.0 ? 1.0 / (lam[c] * sv) : 0.0;
+                Bl[(size_t)r * k + c] = cscale(v, (R)sc);
+            }, As, Bs);
+        return;
+    }
     block_gemm<T, true, true, 8>(
         d.m, k, n, tm * 64, tn * 64,
         [&](int r, int q) { return th[(size_t)r * n + q]; },
@@ -1521,7 +1538,7 @@ __global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
     if (!item_dims(s, w, j, d)) return;
     const int m = d.m, n = d.n, r = w.kout[j], tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int NW = JAC_NT / 64;
-    const double* lamL = d.bond > 0 ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    const double* lamL = (d.bond > 0 && !w.unitw) ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
     for (int i = tid; i < m; i += JAC_NT) {
         const double l = lamL ? lamL[i / d.dl] : 1.0;
         wt[i] = l * l;
@@ -1638,13 +1655,17 @@ __global__ __launch_bounds__(NT) void k_jac_store(DevState s, DevWork w, double*
     T* Bl = site_ptr<T>(s, d.b, d.bond);
     T* Br = site_ptr<T>(s, d.b, d.bond + 1);
     const double inv = 1.0 / sv;
+    // centre moving right (sequential sweep): B_bond = Y diag(1/S), B_{bond+1} = diag(Lambda) V^+
+    const double* lam = w.rmove ? lam_ptr(s, d.b, d.bond) : nullptr;
     for (int e = tid; e < m * k; e += NT) {
         const int i = e / k, c = e % k;
-        Bl[e] = cconv<T>(cscale(Y[(size_t)sel[c] * w.ldy + i], inv));
+        const double sc = lam ? (lam[c] > 0.0 ? 1.0 / (lam[c] * sv) : 0.0) : inv;
+        Bl[e] = cconv<T>(cscale(Y[(size_t)sel[c] * w.ldy + i], sc));
     }
     for (int e = tid; e < k * n; e += NT) {
         const int c = e / n, q = e % n;
-        Br[e] = cconv<T>(cconj(V[(size_t)q * w.vld + sel[c]]));
+        const double2 v = cconj(V[(size_t)q * w.vld + sel[c]]);
+        Br[e] = cconv<T>(lam ? cscale(v, lam[c]) : v);
     }
 }
 
@@ -1673,7 +1694,8 @@ static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_
     const int tkn = (s.chi + 63) / 64;
     prof_begin(prof, TN_K_THETA, st);
     hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-    hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+    if (!w.skip_gate)
+        hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
     prof_end(prof, TN_K_THETA, st);
     prof_begin(prof, TN_K_GRAM, st);
     hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);

@@ -73,8 +73,9 @@ struct tn_state {
     double slot_tau[2];
     bool slot_valid[2];
     Prof prof;
-    // one captured Trotter step (all layers, unmasked) per order, replayed by tebd_step
-    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    // one captured Trotter step (all layers, unmasked) per schedule and order, replayed by tebd_step
+    hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    int schedule = TN_SCHED_LAYER;
     int use_graph = 1;
     // autotuner: Householder variant for n <= 128 chosen by timing on the state's own data
     int tuned = 0;
@@ -83,11 +84,12 @@ struct tn_state {
 };
 
 static void drop_graphs(tn_state* s) {
-    for (int o = 0; o < 3; ++o)
-        if (s->gexec[o]) {
-            hipGraphExecDestroy(s->gexec[o]);
-            s->gexec[o] = nullptr;
-        }
+    for (int sc = 0; sc < 2; ++sc)
+        for (int o = 0; o < 3; ++o)
+            if (s->gexec[sc][o]) {
+                hipGraphExecDestroy(s->gexec[sc][o]);
+                s->gexec[sc][o] = nullptr;
+            }
 }
 
 static inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -621,6 +623,61 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
     return TN_OK;
 }
 
+// Sequential sweep (Sec. 2.3, eq. ShiftCenter): one bond of every unmasked instance per launch
+// sequence, with the orthogonality centre on one of the bond's sites.  gate: the layer's gate
+// in `slot`, or the identity (a centre shift); right: the centre leaves on site bond+1.
+static int run_bond(tn_state* s, int bond, int slot, bool gate, bool right, const unsigned char* mask_dev) {
+    DevState ds = dev_state(s);
+    double* glog = at<double>(s, s->lay.off_glog);
+    double* gwt = at<double>(s, s->lay.off_gwt);
+    for (long i0 = 0; i0 < s->B; i0 += s->chunk) {
+        const int nitems = (int)std::min((long)s->chunk, (long)s->B - i0);
+        DevWork w = chunk_work(s, bond, 1, slot, i0, nitems, mask_dev);
+        w.unitw = 1;
+        w.rmove = right ? 1 : 0;
+        w.skip_gate = gate ? 0 : 1;
+        launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
+        HIPCHK(hipGetLastError());
+    }
+    launch_reduce_items(ds, 1, bond, mask_dev, glog, gwt, s->stream);
+    HIPCHK(hipGetLastError());
+    return TN_OK;
+}
+
+// One Trotter step by the sweep.  Passes (the layers of the step, in order) alternate direction,
+// the first going left to right; before each gate the centre is shifted one bond at a time
+// until it sits on the bond; after the last pass it returns to site 0, so that between steps
+// every tensor but the first is right-canonical (the storage form of the layer schedule).
+static int sweep_step(tn_state* s, const std::vector<std::pair<int, int>>& layers, const unsigned char* mask_dev) {
+    int c = 0, rc;
+    bool right = true;
+    for (auto& ly : layers) {
+        std::vector<int> bonds;
+        for (int b = ly.first; b <= s->L - 2; b += 2) bonds.push_back(b);
+        if (!right) std::reverse(bonds.begin(), bonds.end());
+        for (int b : bonds) {
+            for (; c < b; ++c)
+                if ((rc = run_bond(s, c, 0, false, true, mask_dev))) return rc;
+            for (; c > b + 1; --c)
+                if ((rc = run_bond(s, c - 1, 0, false, false, mask_dev))) return rc;
+            if ((rc = run_bond(s, b, ly.second, true, right, mask_dev))) return rc;
+            c = right ? b + 1 : b;
+        }
+        right = !right;
+    }
+    for (; c > 0; --c)
+        if ((rc = run_bond(s, c - 1, 0, false, false, mask_dev))) return rc;
+    return TN_OK;
+}
+
+static int run_step(tn_state* s, const std::vector<std::pair<int, int>>& layers, const unsigned char* mask_dev) {
+    if (s->schedule == TN_SCHED_SWEEP) return sweep_step(s, layers, mask_dev);
+    int rc;
+    for (auto& ly : layers)
+        if ((rc = run_layer(s, ly.first, ly.second, mask_dev))) return rc;
+    return TN_OK;
+}
+
 // Autotuner: for n <= 128 two Householder kernels exist (MFMA block columns, wave tiles).  On the
 // first Trotter step of a state both run on the Gram matrices of the state's own first chunk
 // (Theta, gate and Gram are recomputed by the real step, the Householder kernels write only
@@ -688,11 +745,10 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
     // only: no memset or copy nodes); gates live in fixed arena slots, so a new dt needs no
     // re-capture.  The library's stream must be a created stream for capture.
     if (s->use_graph && !mdev && !s->prof.on && s->stream != nullptr && n_steps > 0) {
-        if (!s->gexec[order]) {
+        hipGraphExec_t& gx = s->gexec[s->schedule][order];
+        if (!gx) {
             HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-            int crc = TN_OK;
-            for (auto& ly : layers)
-                if ((crc = run_layer(s, ly.first, ly.second, nullptr))) break;
+            const int crc = run_step(s, layers, nullptr);
             hipGraph_t graph = nullptr;
             const hipError_t ce = hipStreamEndCapture(s->stream, &graph);
             if (crc) {
@@ -700,18 +756,17 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
                 return crc;
             }
             if (ce != hipSuccess) return fail(TN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
-            const hipError_t ie = hipGraphInstantiate(&s->gexec[order], graph, nullptr, nullptr, 0);
+            const hipError_t ie = hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0);
             hipGraphDestroy(graph);
             if (ie != hipSuccess) {
-                s->gexec[order] = nullptr;
+                gx = nullptr;
                 return fail(TN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
             }
         }
-        for (int st = 0; st < n_steps; ++st) HIPCHK(hipGraphLaunch(s->gexec[order], s->stream));
+        for (int st = 0; st < n_steps; ++st) HIPCHK(hipGraphLaunch(gx, s->stream));
     } else {
         for (int st = 0; st < n_steps; ++st)
-            for (auto& ly : layers)
-                if ((rc = run_layer(s, ly.first, ly.second, mdev))) return rc;
+            if ((rc = run_step(s, layers, mdev))) return rc;
     }
     if ((rc = check_flags(s))) {
         if (trunc_weight_out)
@@ -918,6 +973,16 @@ extern "C" int tn_graph_enable(void* h, int on) {
     hipStreamSynchronize(s->stream);
     s->use_graph = on != 0;
     if (!s->use_graph) drop_graphs(s);
+    return TN_OK;
+}
+
+extern "C" int tn_schedule(void* h, int schedule) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (schedule != TN_SCHED_LAYER && schedule != TN_SCHED_SWEEP) return fail(TN_EINVAL, "unknown schedule");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->schedule = schedule;
     return TN_OK;
 }
 

@@ -78,7 +78,8 @@ def test_binding_constants_match_header():
              "TN_FP64": api.FP64, "TN_SPLIT": api.SPLIT, "TN_MODE_QT": api.MODE_QT, "TN_MODE_QSD": api.MODE_QSD,
              "TN_MODE_KRAUS": api.MODE_KRAUS, "TN_MODE_QT_SHIFT": api.MODE_QT_SHIFT,
              "TN_MODE_QSD_SHIFT": api.MODE_QSD_SHIFT, "TN_NOISE_GAUSS": api.NOISE_GAUSS,
-             "TN_NOISE_BINARY": api.NOISE_BINARY}
+             "TN_NOISE_BINARY": api.NOISE_BINARY,
+             "TN_SCHED_LAYER": api.SCHED_LAYER, "TN_SCHED_SWEEP": api.SCHED_SWEEP}
     for name, val in pairs.items():
         assert defs[name] == val, name
     for i, k in enumerate(api.K_NAMES):
