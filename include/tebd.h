@@ -193,6 +193,16 @@ int tn_tuning(void* s, int set_variant, int* variant_out, float* ms_out);
  * Returns TN_OK or TN_EINVAL (null handle). */
 int tn_graph_enable(void* s, int on);
 
+/* ---- stream overlap ------------------------------------------------------- */
+
+/* When a layer has more items than one workspace chunk, the arena holds two workspace slots and
+ * the library owns a second stream (default priority): chunks alternate between the stream given
+ * to mps_alloc and that stream, forked after the work already queued and joined back before the
+ * layer's reduction, so kernels of different chunks can share the compute units.  Results do not
+ * depend on it (every item is computed the same way).  on = 0 keeps every chunk on the caller's
+ * stream; on = 1 (the default) allows the overlap.  Returns TN_OK or TN_EINVAL (null handle). */
+int tn_overlap(void* s, int on);
+
 /* ---- Trotter schedule ----------------------------------------------------- */
 
 /* Selects how tebd_step applies a Trotter step (both give the same Trotter product, Sec. 2.3):

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libtebd.so")
 EXPORTS = [
     "mps_arena_bytes", "mps_alloc", "tebd_step", "apply_jumps", "measure_corr", "mps_free",
     "mps_last_error", "mps_instance_tensor_capacity", "mps_instance_lambda_capacity",
-    "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_schedule", "tn_prof_enable",
+    "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_overlap", "tn_schedule", "tn_prof_enable",
     "tn_prof_query",
 ]
 
@@ -70,6 +70,8 @@ def load():
     lib.tn_prof_enable.argtypes = [vp, ctypes.c_int]
     lib.tn_graph_enable.restype = ctypes.c_int
     lib.tn_graph_enable.argtypes = [vp, ctypes.c_int]
+    lib.tn_overlap.restype = ctypes.c_int
+    lib.tn_overlap.argtypes = [vp, ctypes.c_int]
     lib.tn_schedule.restype = ctypes.c_int
     lib.tn_schedule.argtypes = [vp, ctypes.c_int]
     lib.tn_tuning.restype = ctypes.c_int

@@ -222,6 +222,10 @@ class State:
         """Allow (default) or forbid HIP-graph replay of unmasked Trotter steps."""
         _check(self.lib.tn_graph_enable(self.h, 1 if on else 0))
 
+    def overlap(self, on=True):
+        """Allow (default) or forbid running the chunks of a layer on two streams."""
+        _check(self.lib.tn_overlap(self.h, 1 if on else 0))
+
     def schedule(self, sched):
         """SCHED_LAYER (layer-parallel Hastings form) or SCHED_SWEEP (sequential sweep with the
         orthogonality centre, Sec. 2.3) for the following tebd_step calls."""

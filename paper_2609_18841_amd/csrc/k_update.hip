@@ -1687,82 +1687,104 @@ __global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned ch
 // ------------------------------------------------------------------ host launchers
 #include "launch.h"
 
+// One chunk of a layer in five phases (all in stream order on `st`):
+//   0 light: Theta, gate, Gram (+ QR of wide items)      1 heavy: Householder reduction
+//   2 light: eigenvalues (bisection / QL + selection)     3 heavy: eigenvectors (+ QR apply)
+//   4 light: split and the rest
+// Heavy phases hold one or two workgroups per compute unit through their register use; a caller
+// that runs two chunks on two streams can order the heavy phases of both so that light phases of
+// one chunk share the compute units with a heavy phase of the other.
 template <class T>
-static void launch_layer_chunk_t(const DevState& s, const DevWork& w, hipStream_t st, Prof* prof,
+static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase, hipStream_t st, Prof* prof,
                                  double* glog, double* gwt) {
     const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
     const int tkn = (s.chi + 63) / 64;
-    prof_begin(prof, TN_K_THETA, st);
-    hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-    if (!w.skip_gate)
-        hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
-    prof_end(prof, TN_K_THETA, st);
-    prof_begin(prof, TN_K_GRAM, st);
-    hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-    if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    prof_end(prof, TN_K_GRAM, st);
-    prof_begin(prof, TN_K_HETRD, st);
-    if (w.nmax <= HR_N && w.hvar == 1)
-        hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
-    else if (w.nmax <= HR_N)
-        hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
-    else if (w.nmax <= HETRD_LDS_N)
-        hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    else
-        hipLaunchKernelGGL(k_hetrd<false>, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    prof_end(prof, TN_K_HETRD, st);
-    if (w.fb) {
-        // split mode, n <= 128, chi <= 64: bisection + twisted factorization; the logged QL path
-        // runs only on the items that k_bisect or k_tvecs hand over
+    switch (phase) {
+    case 0:
+        prof_begin(prof, TN_K_THETA, st);
+        hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+        if (!w.skip_gate)
+            hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+        prof_end(prof, TN_K_THETA, st);
+        prof_begin(prof, TN_K_GRAM, st);
+        hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+        if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        prof_end(prof, TN_K_GRAM, st);
+        return;
+    case 1:
+        prof_begin(prof, TN_K_HETRD, st);
+        if (w.nmax <= HR_N && w.hvar == 1)
+            hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+        else if (w.nmax <= HR_N)
+            hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+        else if (w.nmax <= HETRD_LDS_N)
+            hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        else
+            hipLaunchKernelGGL(k_hetrd<false>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        prof_end(prof, TN_K_HETRD, st);
+        return;
+    case 2:
         prof_begin(prof, TN_K_STEQR, st);
-        hipLaunchKernelGGL(k_bisect, dim3(w.nitems), dim3(64), 0, st, s, w);
+        if (w.fb) {
+            // split mode, n <= 128, chi <= 64: bisection + twisted factorization; the logged QL
+            // path runs only on the items that k_bisect or k_tvecs hand over
+            hipLaunchKernelGGL(k_bisect, dim3(w.nitems), dim3(64), 0, st, s, w);
+        } else {
+            if (w.nmax <= QL_LDS_N)
+                hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+            else
+                hipLaunchKernelGGL(k_steqr<false>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+            hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, w.jacobi ? 1 : 0);
+        }
         prof_end(prof, TN_K_STEQR, st);
+        return;
+    case 3:
         prof_begin(prof, TN_K_VECS, st);
-        hipLaunchKernelGGL(k_tvecs<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        if (w.fb) {
+            hipLaunchKernelGGL(k_tvecs<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        } else {
+            if (w.nmax <= VF_N && w.vld <= VF_K)
+                hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+            else if ((size_t)w.nmax * w.vld <= VECS_LDS_ELEMS)
+                hipLaunchKernelGGL((k_vecs<T, true>), dim3(w.nitems), dim3(NT), 0, st, s, w);
+            else
+                hipLaunchKernelGGL((k_vecs<T, false>), dim3(w.nitems), dim3(NT), 0, st, s, w);
+            if (w.qr_route) hipLaunchKernelGGL(k_qr_apply<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        }
         prof_end(prof, TN_K_VECS, st);
-        hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
-        hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 0);
-        hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        return;
+    default:
+        if (w.fb) {
+            hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+            hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 0);
+            hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        }
         prof_begin(prof, TN_K_SPLIT, st);
-        hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+        if (w.jacobi) {
+            const int tr = (w.nmax + 63) / 64;
+            hipLaunchKernelGGL(k_jac_y, dim3(tm * tr, w.nitems), dim3(NT), 0, st, s, w, tr);
+            hipLaunchKernelGGL(k_jacobi, dim3(w.nitems), dim3(JAC_NT), 0, st, s, w);
+            hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 2);
+            hipLaunchKernelGGL(k_jac_store<T>, dim3(w.nitems), dim3(NT), 0, st, s, w, glog, gwt);
+        } else {
+            hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
+        }
         prof_end(prof, TN_K_SPLIT, st);
         return;
     }
-    prof_begin(prof, TN_K_STEQR, st);
-    if (w.nmax <= QL_LDS_N)
-        hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+}
+
+void launch_layer_phase(int prec, const DevState& s, const DevWork& w, int phase, hipStream_t st, Prof* prof,
+                        double* glog, double* gwt) {
+    if (prec == 0)
+        launch_layer_phase_t<double2>(s, w, phase, st, prof, glog, gwt);
     else
-        hipLaunchKernelGGL(k_steqr<false>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
-    hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, w.jacobi ? 1 : 0);
-    prof_end(prof, TN_K_STEQR, st);
-    prof_begin(prof, TN_K_VECS, st);
-    if (w.nmax <= VF_N && w.vld <= VF_K)
-        hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    else if ((size_t)w.nmax * w.vld <= VECS_LDS_ELEMS)
-        hipLaunchKernelGGL((k_vecs<T, true>), dim3(w.nitems), dim3(NT), 0, st, s, w);
-    else
-        hipLaunchKernelGGL((k_vecs<T, false>), dim3(w.nitems), dim3(NT), 0, st, s, w);
-    if (w.qr_route) hipLaunchKernelGGL(k_qr_apply<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
-    prof_end(prof, TN_K_VECS, st);
-    prof_begin(prof, TN_K_SPLIT, st);
-    if (w.jacobi) {
-        const int tr = (w.nmax + 63) / 64;
-        hipLaunchKernelGGL(k_jac_y, dim3(tm * tr, w.nitems), dim3(NT), 0, st, s, w, tr);
-        hipLaunchKernelGGL(k_jacobi, dim3(w.nitems), dim3(JAC_NT), 0, st, s, w);
-        hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 2);
-        hipLaunchKernelGGL(k_jac_store<T>, dim3(w.nitems), dim3(NT), 0, st, s, w, glog, gwt);
-    } else {
-        hipLaunchKernelGGL(k_split<T>, dim3(tm * tkn, w.nitems), dim3(NT), 0, st, s, w, tkn, glog, gwt);
-    }
-    prof_end(prof, TN_K_SPLIT, st);
+        launch_layer_phase_t<float2>(s, w, phase, st, prof, glog, gwt);
 }
 
 void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream_t st, Prof* prof,
                         double* glog, double* gwt) {
-    if (prec == 0)
-        launch_layer_chunk_t<double2>(s, w, st, prof, glog, gwt);
-    else
-        launch_layer_chunk_t<float2>(s, w, st, prof, glog, gwt);
+    for (int ph = 0; ph < 5; ++ph) launch_layer_phase(prec, s, w, ph, st, prof, glog, gwt);
 }
 
 template <class T>

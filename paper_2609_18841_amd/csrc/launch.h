@@ -26,6 +26,10 @@ void prof_end(Prof* p, int id, hipStream_t st);
 // update pipeline (k_update.hip)
 void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream_t st, Prof* prof,
                         double* glog, double* gwt);
+// the same chunk in five phases (0 light, 1 heavy, 2 light, 3 heavy, 4 light); running phases 0..4
+// in order equals launch_layer_chunk
+void launch_layer_phase(int prec, const DevState& s, const DevWork& w, int phase, hipStream_t st, Prof* prof,
+                        double* glog, double* gwt);
 void launch_reduce_items(const DevState& s, int nb, int parity, const unsigned char* mask, const double* glog,
                          const double* gwt, hipStream_t st);
 // pieces of the pipeline used by the autotuner: Theta, gate and Gram of a chunk (pure functions

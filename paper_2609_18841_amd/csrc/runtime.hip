@@ -81,7 +81,29 @@ struct tn_state {
     int tuned = 0;
     int hvar = 0;
     float tune_ms[2] = {0.0f, 0.0f};
+    // chunks of one layer alternate between `stream` and `aux` (a stream the library owns, default
+    // priority), each with its own workspace slot, so that kernels of different chunks can share
+    // the compute units; joined back into `stream` before the layer's reduction
+    int nslots = 1;
+    int overlap = 1;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    Prof prof2;  // timing of the work launched on aux
+    ~tn_state() {
+        if (aux) {
+            hipStreamSynchronize(aux);
+            hipStreamDestroy(aux);
+        }
+        for (hipEvent_t e : {ev_fork, ev_join})
+            if (e) hipEventDestroy(e);
+    }
 };
+
+// workspace slots: two when a layer can span more than one chunk
+static int workspace_slots(int L, int B, int chunk) {
+    const long items = (long)B * ((L - 1 + 1) / 2);
+    return items > chunk ? 2 : 1;
+}
 
 static void drop_graphs(tn_state* s) {
     for (int sc = 0; sc < 2; ++sc)
@@ -103,7 +125,7 @@ static int physical_dims(int kind, int L, int chik, const std::vector<int>& jsit
 }
 
 static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax, int prec, int chunk, int nbm,
-                           int njump, int logcap) {
+                           int njump, int logcap, int nslots) {
     const size_t esz = prec == 0 ? 16 : 8;
     const size_t site_cap = (size_t)chi * dmax * chi;
     const int mmax = chi * dmax, nmax = dmax * chi;
@@ -168,7 +190,7 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.m_Y = m; m = al(m + (size_t)nbm * L * chi * dmax * chi * esz);
     ly.m_W = m; m = al(m + (size_t)nbm * chi * dmax * chi * esz);
     ly.m_bytes = m;
-    ly.ws_bytes = std::max(ly.u_bytes, ly.m_bytes);
+    ly.ws_bytes = std::max((size_t)nslots * ly.u_bytes, ly.m_bytes);
     ly.total = ly.off_ws + ly.ws_bytes;
     (void)kind;
 }
@@ -209,7 +231,8 @@ extern "C" size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int c
     int chunk = chunk_items > 0 ? chunk_items : default_chunk(L, batch, chi_max, dmax);
     int nbm = default_nbm(batch, L, chi_max);
     Layout ly;
-    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, TN_MAX_JUMPS, log_capacity(dmax * chi_max));
+    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, TN_MAX_JUMPS, log_capacity(dmax * chi_max),
+                   workspace_slots(L, batch, chunk));
     return ly.total;
 }
 
@@ -301,7 +324,9 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
     s->logcap = log_capacity(s->nmax);
     s->gstride = 256;
     s->nbmax = (L - 1 + 1) / 2;
-    compute_layout(s->lay, kind, L, batch, chi_max, s->dmax, precision, s->chunk, s->nbm, TN_MAX_JUMPS, s->logcap);
+    s->nslots = workspace_slots(L, batch, s->chunk);
+    compute_layout(s->lay, kind, L, batch, chi_max, s->dmax, precision, s->chunk, s->nbm, TN_MAX_JUMPS, s->logcap,
+                   s->nslots);
     if (arena_bytes < s->lay.total) {
         size_t need = s->lay.total;
         delete s;
@@ -311,6 +336,15 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
     }
     s->arena = reinterpret_cast<char*>(arena);
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (s->nslots == 2) {
+        bool ok = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
+        for (hipEvent_t* e : {&s->ev_fork, &s->ev_join})
+            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            delete s;
+            return fail(TN_EHIP, "creating the second stream or its events failed");
+        }
+    }
     s->slot_valid[0] = s->slot_valid[1] = false;
     // constant tables
     int rc;
@@ -370,11 +404,12 @@ extern "C" int mps_free(void* h) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     if (!s) return fail(TN_EINVAL, "null handle");
     hipStreamSynchronize(s->stream);
-    for (int k = 0; k < TN_K_COUNT; ++k)
-        for (auto& pr : s->prof.ev[k]) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
-        }
+    for (Prof* p : {&s->prof, &s->prof2})
+        for (int k = 0; k < TN_K_COUNT; ++k)
+            for (auto& pr : p->ev[k]) {
+                hipEventDestroy(pr.first);
+                hipEventDestroy(pr.second);
+            }
     drop_graphs(s);
     delete s;
     return TN_OK;
@@ -558,8 +593,8 @@ static int check_flags(tn_state* s) {
 // ------------------------------------------------------------------ TEBD
 // workspace view of the chunk of items [i0, i0 + nitems) of one layer
 static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, int nitems,
-                          const unsigned char* mask_dev) {
-    char* ws = s->arena + s->lay.off_ws;
+                          const unsigned char* mask_dev, int wslot = 0) {
+    char* ws = s->arena + s->lay.off_ws + (size_t)wslot * s->lay.u_bytes;
     DevWork w;
     w.item0 = (int)i0;
     w.nitems = nitems;
@@ -612,11 +647,27 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
     const long total = (long)s->B * nb;
     double* glog = at<double>(s, s->lay.off_glog);
     double* gwt = at<double>(s, s->lay.off_gwt);
-    for (long i0 = 0; i0 < total; i0 += s->chunk) {
+    // Items of one layer are independent.  With two workspace slots, odd chunks run on aux with
+    // their own slot, forked after the work already on the main stream and joined back before the
+    // layer's reduction.  (Ordering the heavy phases of the two streams into one chain, so that
+    // light phases of one chunk run beside heavy phases of the other, measured no faster than
+    // this plain alternation: the kernels share the compute units' LDS bandwidth.)
+    const bool two = s->nslots == 2 && s->overlap && s->aux && total > s->chunk;
+    if (two) {
+        HIPCHK(hipEventRecord(s->ev_fork, s->stream));
+        HIPCHK(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
+    }
+    int c = 0;
+    for (long i0 = 0; i0 < total; i0 += s->chunk, ++c) {
         const int nitems = (int)std::min((long)s->chunk, total - i0);
-        DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev);
-        launch_layer_chunk(s->prec, ds, w, s->stream, &s->prof, glog, gwt);
+        const int ws = two ? (c & 1) : 0;
+        DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws);
+        launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
         HIPCHK(hipGetLastError());
+    }
+    if (two) {
+        HIPCHK(hipEventRecord(s->ev_join, s->aux));
+        HIPCHK(hipStreamWaitEvent(s->stream, s->ev_join, 0));
     }
     launch_reduce_items(ds, nb, parity, mask_dev, glog, gwt, s->stream);
     HIPCHK(hipGetLastError());
@@ -976,6 +1027,16 @@ extern "C" int tn_graph_enable(void* h, int on) {
     return TN_OK;
 }
 
+extern "C" int tn_overlap(void* h, int on) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->overlap = on != 0;
+    drop_graphs(s);  // captured steps carry the old stream pattern
+    return TN_OK;
+}
+
 extern "C" int tn_schedule(void* h, int schedule) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     g_err.clear();
@@ -991,15 +1052,17 @@ extern "C" int tn_prof_enable(void* h, int on) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     if (!s) return fail(TN_EINVAL, "null handle");
     hipStreamSynchronize(s->stream);
-    for (int k = 0; k < TN_K_COUNT; ++k) {
-        for (auto& pr : s->prof.ev[k]) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+    for (Prof* p : {&s->prof, &s->prof2}) {
+        for (int k = 0; k < TN_K_COUNT; ++k) {
+            for (auto& pr : p->ev[k]) {
+                hipEventDestroy(pr.first);
+                hipEventDestroy(pr.second);
+            }
+            p->ev[k].clear();
+            p->open[k] = nullptr;
         }
-        s->prof.ev[k].clear();
-        s->prof.open[k] = nullptr;
+        p->on = on != 0;
     }
-    s->prof.on = on != 0;
     return TN_OK;
 }
 
@@ -1009,12 +1072,16 @@ extern "C" int tn_prof_query(void* h, int kernel_id, double* total_ms, long long
     if (kernel_id < 0 || kernel_id >= TN_K_COUNT) return fail(TN_EINVAL, "bad kernel id");
     HIPCHK(hipStreamSynchronize(s->stream));
     double tot = 0.0;
-    for (auto& pr : s->prof.ev[kernel_id]) {
-        float ms = 0.0f;
-        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
-        tot += ms;
+    long long cnt = 0;
+    for (Prof* p : {&s->prof, &s->prof2}) {
+        for (auto& pr : p->ev[kernel_id]) {
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            tot += ms;
+        }
+        cnt += (long long)p->ev[kernel_id].size();
     }
     if (total_ms) *total_ms = tot;
-    if (launches) *launches = (long long)s->prof.ev[kernel_id].size();
+    if (launches) *launches = cnt;
     return TN_OK;
 }

@@ -53,3 +53,29 @@ def test_graph_replay_with_changing_dt_and_masked_steps():
         outs.append((C_each, nrm))
         st.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_two_stream_overlap_is_bit_identical():
+    """Layers with more items than one workspace chunk run their chunks on two streams; every
+    item is computed the same way, so the state equals the one-stream run bit for bit (eager and
+    graph replay)."""
+    L, chi, B, dt = 64, 16, 320, 0.01   # 320 * 32 = 10240 items per layer > one chunk
+    occ = tn_inputs.neel(L)
+    nz = tn_inputs.normals(5, (3, B * 2 * 2))
+    res = []
+    for overlap, graph in ((False, False), (True, False), (True, True)):
+        st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ, precision=api.SPLIT, sv_cutoff=1e-6)
+        st.overlap(overlap)
+        st.graph_enable(graph)
+        for k in range(3):
+            st.tebd_step(dt, order=1)
+            st.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
+        res.append([st.get_instance(b) for b in (0, 161, B - 1)])
+        st.close()
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for ta, tb in zip(a[0], b[0]):
+                assert np.array_equal(ta, tb)
+            for la, lb in zip(a[1], b[1]):
+                assert np.array_equal(la, lb)
+            assert a[2] == b[2]
