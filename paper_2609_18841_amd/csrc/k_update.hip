@@ -3,8 +3,8 @@
 // One Trotter layer is a set of independent work items (instance b, bond) --
 // all bonds of one parity of every unmasked instance commute (Sec. 2.3).  Each
 // item goes through
-//   k_theta   M = B_bond . B_{bond+1}               (complex GEMM, eq. Theta)
-//   k_gate    Theta~ = G (x) M on the physical pair  (eq. Theta / eq. ThetaPurified)
+//   k_theta_gate  Theta~ = G (x) (B_bond . B_{bond+1})  (complex GEMM with the gate applied to the
+//             staged output tile, eq. Theta / eq. ThetaPurified; plain k_theta for centre shifts)
 //   k_gram    H = Theta~^+ diag(Lambda_{bond-1}^2) Theta~   (FP64, lower triangle)
 //   k_hetrd   Householder reduction H = Q T Q^+, T real tridiagonal (FP64)
 //   k_steqr   implicit QL on T, logging every Givens rotation (FP64)
@@ -73,38 +73,57 @@ __global__ __launch_bounds__(NT) void k_theta(DevState s, DevWork w, int tiles_n
         [&](int r, int c, T v) { out[(size_t)r * n + c] = v; }, As, Bs);
 }
 
-// ------------------------------------------------------------------ gate on the physical pair
-template <class T>
-__global__ __launch_bounds__(NT) void k_gate(DevState s, DevWork w) {
-    typedef typename real_of<T>::type R;
+// Theta~ = G (x) (B_bond . B_{bond+1}) in one pass (eq. Theta): the GEMM runs over a virtual
+// column numbering in which a 64-wide tile holds cw = 64/d_r values of c for every q (column
+// V -> q = (V % 64) / cw, c = (V / 64) cw + (V % 64) % cw), so the d_l d_r entries that the gate
+// mixes, rows (a, p) and columns (q, c), all land in one tile.  The tile is staged in LDS and
+// the gate applied on the way to memory.
+template <class T, int DM>
+__global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int tiles_n) {
+    // the output tile reuses the operand staging space: block_gemm ends its k loop with a
+    // barrier, after which the staging buffers are dead
+    __shared__ T smem[64 * 64];
     __shared__ T G[256];
+    T* As = smem;
+    T* Bs = smem + 8 * 64;
+    T* tile = smem;
     ItemDims d;
     if (!item_dims(s, w, blockIdx.y, d)) return;
-    const int D = d.dl * d.dr;
+    const int dl = d.dl, dr = d.dr, D = dl * dr, cw = 64 / dr, chir = d.chir, n = d.n;
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    if (tm * 64 >= d.m || tn * cw >= chir) return;
     const double2* g = w.gates + (size_t)d.bond * w.gstride;
     for (int e = threadIdx.x; e < D * D; e += NT) G[e] = cconv<T>(g[e]);
+    const T* P = site_ptr<T>(s, d.b, d.bond);
+    const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
+    T* out = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    const int K = d.chim, m0 = tm * 64;
+    block_gemm<T, true, true, 8>(
+        d.m, tiles_n * 64, K, m0, tn * 64,
+        [&](int r, int k) { return P[(size_t)r * K + k]; },
+        [&](int k, int V) {
+            const int loc = V & 63, q = loc / cw, c = (V >> 6) * cw + loc % cw;
+            return c < chir ? Q[(size_t)k * n + q * chir + c] : czero<T>();
+        },
+        [&](int r, int V, T v) { tile[(r - m0) * 64 + (V & 63)] = v; }, As, Bs);
     __syncthreads();
-    T* th = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
-    const int n = d.n, chir = d.chir, dl = d.dl, dr = d.dr;
-    for (int idx = blockIdx.x * NT + threadIdx.x; idx < d.chil * chir; idx += gridDim.x * NT) {
-        int a = idx / chir, c = idx % chir;
-        T v[16];
+    const int npair = (64 / dl) * cw;
+    for (int e = threadIdx.x; e < npair; e += NT) {
+        const int al = e / cw, cl = e % cw, c = tn * cw + cl;
+        const int r0 = m0 + al * dl;
+        if (c >= chir || r0 >= d.m) continue;
+        T v[DM];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            if (e < D) {
-                int p = e / dr, q = e % dr;
-                v[e] = th[(size_t)(a * dl + p) * n + q * chir + c];
-            }
-        }
+        for (int x = 0; x < DM; ++x)
+            if (x < D) v[x] = tile[(al * dl + x / dr) * 64 + (x % dr) * cw + cl];
 #pragma unroll
-        for (int o = 0; o < 16; ++o) {
+        for (int o = 0; o < DM; ++o) {
             if (o < D) {
                 T acc = czero<T>();
 #pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    if (e < D) cfma(acc, G[o * D + e], v[e]);
-                int p = o / dr, q = o % dr;
-                th[(size_t)(a * dl + p) * n + q * chir + c] = acc;
+                for (int x = 0; x < DM; ++x)
+                    if (x < D) cfma(acc, G[o * D + x], v[x]);
+                out[(size_t)(r0 + o / dr) * n + (o % dr) * chir + c] = acc;
             }
         }
     }
@@ -1708,9 +1727,16 @@ static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase,
     switch (phase) {
     case 0:
         prof_begin(prof, TN_K_THETA, st);
-        hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-        if (!w.skip_gate)
-            hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+        if (w.skip_gate) {
+            hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+        } else {
+            // virtual column tiles: 64/d_r values of c per tile, for the largest d_r
+            const int tv = (s.chi * s.dmax + 63) / 64;
+            if (s.dmax == 2)
+                hipLaunchKernelGGL((k_theta_gate<T, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
+            else
+                hipLaunchKernelGGL((k_theta_gate<T, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
+        }
         prof_end(prof, TN_K_THETA, st);
         prof_begin(prof, TN_K_GRAM, st);
         hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
@@ -1796,8 +1822,11 @@ void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream
 template <class T>
 static void launch_update_prefix_t(const DevState& s, const DevWork& w, hipStream_t st) {
     const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
-    hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-    hipLaunchKernelGGL(k_gate<T>, dim3(((s.chi * s.chi) + NT - 1) / NT, w.nitems), dim3(NT), 0, st, s, w);
+    const int tv = (s.chi * s.dmax + 63) / 64;
+    if (s.dmax == 2)
+        hipLaunchKernelGGL((k_theta_gate<T, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
+    else
+        hipLaunchKernelGGL((k_theta_gate<T, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
     hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
     if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
 }
