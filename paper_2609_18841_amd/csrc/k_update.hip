@@ -721,14 +721,24 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
     // row 0: block 0, local row 0 (g = 0, k = 0) of every wave
     if (g == 0) rowold[0][myc] = mk(are[0][0], aim[0][0]);
     __syncthreads();
-    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vpriv[0][wv], wv == 0, dd, ee, tau,
-                              refl);
+    const int wlast = (n - 1) >> 4;  // owns column n-1: live at every step, writes d, e, tau, v
+    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vpriv[0][wv], wv == wlast, dd, ee,
+                              tau, refl);
     const bool cols_live0 = C0 < n;
     for (int i = 0; i + 1 < n; ++i) {
         const double2* vc_ = vpriv[i & 1][wv];
         double2* vn_ = vpriv[(i + 1) & 1][wv];
         const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
         const bool cols_live = cols_live0 && (C0 + 15 > i);
+        if (!cols_live) {
+            // every column of this wave is reduced: nothing it would compute is read again
+            // (later steps use entries > i only); it keeps the barrier count and adds a zero
+            // to p^+ v
+            if (lane == 0) qpart[wv] = mk(0.0, 0.0);
+            __syncthreads();
+            __syncthreads();
+            continue;
+        }
         // p_c = tau sum_r conj(A_rc) v_r for the wave's columns c = C0 + cl
         double pr = 0.0, pim = 0.0;
         if (act && cols_live) {
@@ -799,8 +809,8 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
         }
         double2 tvn = mk(0.0, 0.0);
         if (i + 2 < n) {
-            tvn = hr_reflector(i + 1, n, lane, x0, x1, vn_, wv == 0, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
-        } else if (wv == 0) {
+            tvn = hr_reflector(i + 1, n, lane, x0, x1, vn_, wv == wlast, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
+        } else if (wv == wlast) {
             const double2 xd = (n - 1) < 64 ? x0 : x1;
             const double dl = readlane_f64(xd.x, (n - 1) & 63);
             if (lane == 0) {
