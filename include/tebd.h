@@ -233,8 +233,12 @@ int tn_schedule(void* s, int schedule);
 
 /* Enable (1) or disable (0) per-kernel event timing; enabling resets the totals. */
 int tn_prof_enable(void* s, int on);
-/* Total milliseconds and launch count recorded for a kernel id since enabling. */
+/* Total milliseconds and launch count recorded for a kernel id since enabling (launches on both
+ * streams; with two streams, concurrent launches each count their full duration). */
 int tn_prof_query(void* s, int kernel_id, double* total_ms, long long* launches);
+/* Wall milliseconds since enabling during which at least one launch of the kernel id was running
+ * (union of the launch intervals of both streams).  Returns TN_OK or TN_EINVAL. */
+int tn_prof_busy(void* s, int kernel_id, double* busy_ms);
 
 #ifdef __cplusplus
 }

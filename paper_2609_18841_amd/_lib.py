@@ -10,7 +10,7 @@ EXPORTS = [
     "mps_arena_bytes", "mps_alloc", "tebd_step", "apply_jumps", "measure_corr", "mps_free",
     "mps_last_error", "mps_instance_tensor_capacity", "mps_instance_lambda_capacity",
     "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_overlap", "tn_schedule", "tn_prof_enable",
-    "tn_prof_query",
+    "tn_prof_query", "tn_prof_busy",
 ]
 
 
@@ -78,5 +78,7 @@ def load():
     lib.tn_tuning.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
     lib.tn_prof_query.restype = ctypes.c_int
     lib.tn_prof_query.argtypes = [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.tn_prof_busy.restype = ctypes.c_int
+    lib.tn_prof_busy.argtypes = [vp, ctypes.c_int, dp]
     _lib = lib
     return lib

@@ -236,3 +236,9 @@ class State:
         n = ctypes.c_longlong()
         _check(self.lib.tn_prof_query(self.h, kid, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def prof_busy(self, kid):
+        """Wall ms during which some launch of kernel id `kid` was running (both streams)."""
+        ms = ctypes.c_double()
+        _check(self.lib.tn_prof_busy(self.h, kid, ctypes.byref(ms)))
+        return ms.value

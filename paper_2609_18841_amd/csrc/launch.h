@@ -17,6 +17,7 @@
 // Per-kernel event timing on the library stream.
 struct Prof {
     bool on = false;
+    hipEvent_t ref = nullptr;  // recorded when timing starts: common origin for both streams
     hipEvent_t open[TN_K_COUNT] = {};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[TN_K_COUNT];
 };

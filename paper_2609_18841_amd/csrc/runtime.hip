@@ -410,6 +410,7 @@ extern "C" int mps_free(void* h) {
                 hipEventDestroy(pr.first);
                 hipEventDestroy(pr.second);
             }
+    if (s->prof.ref) hipEventDestroy(s->prof.ref);
     drop_graphs(s);
     delete s;
     return TN_OK;
@@ -1063,6 +1064,48 @@ extern "C" int tn_prof_enable(void* h, int on) {
         }
         p->on = on != 0;
     }
+    if (s->prof.ref) {
+        hipEventDestroy(s->prof.ref);
+        s->prof.ref = nullptr;
+    }
+    if (on) {
+        HIPCHK(hipEventCreate(&s->prof.ref));
+        HIPCHK(hipEventRecord(s->prof.ref, s->stream));
+    }
+    return TN_OK;
+}
+
+// Wall time during which at least one launch of the bucket was running (union of the launch
+// intervals of both streams, measured from the common reference event).
+extern "C" int tn_prof_busy(void* h, int kernel_id, double* busy_ms) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (kernel_id < 0 || kernel_id >= TN_K_COUNT) return fail(TN_EINVAL, "bad kernel id");
+    if (!busy_ms) return fail(TN_EINVAL, "busy_ms is null");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *busy_ms = 0.0;
+    if (!s->prof.ref) return TN_OK;
+    std::vector<std::pair<double, double>> iv;
+    for (Prof* p : {&s->prof, &s->prof2})
+        for (auto& pr : p->ev[kernel_id]) {
+            float a = 0.0f, b = 0.0f;
+            HIPCHK(hipEventElapsedTime(&a, s->prof.ref, pr.first));
+            HIPCHK(hipEventElapsedTime(&b, s->prof.ref, pr.second));
+            iv.push_back(std::make_pair((double)a, (double)b));
+        }
+    std::sort(iv.begin(), iv.end());
+    double tot = 0.0, lo = 0.0, hi = -1.0;
+    for (auto& x : iv) {
+        if (x.first > hi) {
+            if (hi > lo) tot += hi - lo;
+            lo = x.first;
+            hi = x.second;
+        } else if (x.second > hi) {
+            hi = x.second;
+        }
+    }
+    if (hi > lo) tot += hi - lo;
+    *busy_ms = tot;
     return TN_OK;
 }
 
