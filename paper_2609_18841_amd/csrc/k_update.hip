@@ -1144,38 +1144,34 @@ __device__ __forceinline__ void vf_backtransform(const DevState& s, const DevWor
     const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
     const double2* tau = w.tau + (size_t)j * w.nmax;
     // reflector rows stream from memory one step ahead of their use: row i is in registers
-    // (cur) while row i+1 is applied, so the global-memory latency overlaps the arithmetic
-    double2 cur = (n >= 2 && tid < 1) ? refl[(size_t)(n - 2) * w.nmax + tid] : mk(0.0, 0.0);
+    // (cur) while row i+1 is applied, so the global-memory latency overlaps the arithmetic.
+    // vbuf holds the reflector zero-padded to full length (vbuf[r] = v_r, 0 for r <= i or r >= n),
+    // so the row loops below run without branches and their LDS reads issue together
+    double2 cur = (n >= 2 && tid == n - 1) ? refl[(size_t)(n - 2) * w.nmax] : mk(0.0, 0.0);
     double2 tv_cur = n >= 2 ? tau[n - 2] : mk(0.0, 0.0);
     for (int i = n - 2; i >= 0; --i) {
-        const int len = n - 1 - i;
         const double2 tv = tv_cur;
         __syncthreads();  // the previous reflector is no longer read from vbuf / part
-        if (tid < len) vbuf[tid] = cur;
+        if (tid < VF_N) vbuf[tid] = cur;
         if (i > 0) {
-            cur = tid < len + 1 ? refl[(size_t)(i - 1) * w.nmax + tid] : mk(0.0, 0.0);
+            // next reflector (i-1): entries r = i .. n-1 hold v at offset r - i
+            cur = (tid >= i && tid < n) ? refl[(size_t)(i - 1) * w.nmax + (tid - i)] : mk(0.0, 0.0);
             tv_cur = tau[i - 1];
         }
         if (tv.x == 0.0 && tv.y == 0.0) continue;  // uniform across the block
         __syncthreads();
         double2 acc = mk(0.0, 0.0);
 #pragma unroll
-        for (int t = 0; t < VF_N / 4; ++t) {
-            const int r = g + 4 * t;
-            if (r >= i + 1 && r < n) cfmac(acc, vbuf[r - i - 1], z[t]);
-        }
+        for (int t = 0; t < VF_N / 4; ++t) cfmac(acc, vbuf[g + 4 * t], z[t]);
         part[tid] = acc;
         __syncthreads();
         double2 wv = cadd(cadd(part[col], part[64 + col]), cadd(part[128 + col], part[192 + col]));
         wv = cmul(tv, wv);
 #pragma unroll
         for (int t = 0; t < VF_N / 4; ++t) {
-            const int r = g + 4 * t;
-            if (r >= i + 1 && r < n) {
-                double2 u = cmul(vbuf[r - i - 1], wv);
-                z[t].x -= u.x;
-                z[t].y -= u.y;
-            }
+            const double2 u = cmul(vbuf[g + 4 * t], wv);
+            z[t].x -= u.x;
+            z[t].y -= u.y;
         }
     }
     double2* V = w.V + (size_t)j * w.nmax * w.vld;
