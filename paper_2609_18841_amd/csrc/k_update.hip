@@ -676,8 +676,29 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
 //   (real and imaginary part) with [v_r, w_r] as the 16 x 4 operand and [w_c; v_c] as 4 x 16.
 typedef double hm_d4 __attribute__((ext_vector_type(4)));
 
+// x + (x of lane l ^ 16) and x + (x of lane l ^ 32) in the VALU: swapping a value with a copy of
+// itself across half-rows (v_permlane16_swap) or half-waves (v_permlane32_swap) leaves the lane
+// and its partner in the two results, so their sum is the pairwise sum (no LDS round trip)
+__device__ __forceinline__ double xsum16(double x) {
+    const unsigned lo = __double2loint(x), hi = __double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+__device__ __forceinline__ double xsum32(double x) {
+    const unsigned lo = __double2loint(x), hi = __double2hiint(x);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+// a_g for the lane's row group g, as a chain of plain selects (v_cndmask) rather than branches
 __device__ __forceinline__ double hm_pick(int g, double a0, double a1, double a2, double a3) {
-    return g == 0 ? a0 : (g == 1 ? a1 : (g == 2 ? a2 : a3));
+    double r = a0;
+    r = g == 1 ? a1 : r;
+    r = g == 2 ? a2 : r;
+    r = g == 3 ? a3 : r;
+    return r;
 }
 
 __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
@@ -757,10 +778,8 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
                 }
             }
             // sum over the four row groups (lanes cl, cl+16, cl+32, cl+48)
-            pr += __shfl_xor(pr, 16);
-            pim += __shfl_xor(pim, 16);
-            pr += __shfl_xor(pr, 32);
-            pim += __shfl_xor(pim, 32);
+            pr = xsum32(xsum16(pr));
+            pim = xsum32(xsum16(pim));
         }
         const double2 pc = (act && myc > i && myc < n) ? cmul(tv, mk(pr, pim)) : mk(0.0, 0.0);
         if (act) {
