@@ -178,7 +178,9 @@ int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 
 /* For n <= 128 the Householder reduction has two kernels (FP64 MFMA block columns = 0, wave
  * tiles = 1).  The first tebd_step of a state times both on the Gram matrices of its own first
- * chunk (median of three) and keeps the faster one.  tn_tuning reports the choice
+ * chunk (median of three) when that chunk holds at least 2048 items, and takes the wave-tile
+ * kernel only when it is more than 5 % faster; smaller states keep kernel 0 untimed, so the
+ * choice does not follow timing noise.  tn_tuning reports the choice
  * (variant_out, may be NULL) and the median times in ms (ms_out[2], may be NULL; zero before
  * tuning or when n > 128); set_variant 0 or 1 overrides the choice, -1 only reports.
  * Returns TN_OK or TN_EINVAL. */

@@ -53,6 +53,7 @@ template <class To, class From> __host__ __device__ __forceinline__ To cconv(Fro
 #define TN_FLAG_NOCONV  1
 #define TN_FLAG_LOGFULL 2
 #define TN_FLAG_NAN     4
+#define TN_FLAG_JACOBI  8   // one-sided Jacobi refinement did not converge
 
 // ---------------------------------------------------------------- device view of a state
 // Everything a kernel needs to locate tensors, bond weights and dimensions of

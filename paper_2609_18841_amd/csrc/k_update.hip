@@ -1608,7 +1608,16 @@ __global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
     __syncthreads();
     double total = 0.0;
     for (int q = 0; q < NW; ++q) total += redv[q];
+    // A pair (p, q) is rotated when its coupling g = |y_p^+ W y_q| exceeds both the relative
+    // tolerance eps sqrt(m) |y_p| |y_q| and an absolute floor (m eps)^2 sum sigma^2.  The mixing
+    // that the Gram basis leaves between directions is about eps sigma_0^2, far above the floor,
+    // so it is always removed; what a rotation leaves behind in floating point is below it, so
+    // the sweeps end.  Without the floor, pairs involving columns near the rounding level of
+    // Y = Theta~ V (absolute errors about eps sigma_0) keep re-triggering the relative test.
+    // A coupling left below the floor changes the state by about g / sigma_max.  Columns below
+    // eps of the total are numerically zero and never rotated.
     const double floor2 = DBL_EPSILON * DBL_EPSILON * total;
+    const double gfloor = ((double)m * DBL_EPSILON) * ((double)m * DBL_EPSILON) * total;
     const double tol = DBL_EPSILON * sqrt((double)m);
     const int R = r + (r & 1);
     int sweep = 0;
@@ -1644,7 +1653,7 @@ __global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
                 cx = wave_sum(cx);
                 cy = wave_sum(cy);
                 const double g = sqrt(cx * cx + cy * cy);
-                if (!(app > floor2 && aqq > floor2) || !(g > tol * sqrt(app * aqq))) continue;
+                if (!(app > floor2 && aqq > floor2) || !(g > tol * sqrt(app * aqq)) || !(g > gfloor)) continue;
                 // rotate (p, q~ = conj(ph) q), ph = c/|c|, by the real Jacobi angle of [[app, g], [g, aqq]]
                 const double zeta = (aqq - app) / (2.0 * g);
                 const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -1672,7 +1681,7 @@ __global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
         __syncthreads();
         if (done) break;
     }
-    if (sweep == JAC_SWEEPS && tid == 0) atomicOr(w.flags, TN_FLAG_NOCONV);
+    if (sweep == JAC_SWEEPS && tid == 0) atomicOr(w.flags, TN_FLAG_JACOBI);
     // squared singular values = weighted column norms (into the eigenvalue slot for k_select)
     for (int c = wv; c < r; c += NW) {
         double q2 = 0.0;

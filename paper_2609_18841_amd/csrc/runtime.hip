@@ -586,7 +586,8 @@ static int check_flags(tn_state* s) {
         HIPCHK(hipMemsetAsync(s->arena + s->lay.off_flags, 0, 4, s->stream));
         if (flags & TN_FLAG_NAN) return fail(TN_ENUMERIC, "NaN in a two-site update");
         if (flags & TN_FLAG_LOGFULL) return fail(TN_ENOCONV, "rotation log capacity exceeded");
-        if (flags & TN_FLAG_NOCONV) return fail(TN_ENOCONV, "tridiagonal QL or Jacobi sweeps did not converge");
+        if (flags & TN_FLAG_NOCONV) return fail(TN_ENOCONV, "tridiagonal QL did not converge");
+        if (flags & TN_FLAG_JACOBI) return fail(TN_ENOCONV, "one-sided Jacobi refinement did not converge");
     }
     return TN_OK;
 }
@@ -734,6 +735,11 @@ static int run_step(tn_state* s, const std::vector<std::pair<int, int>>& layers,
 // first Trotter step of a state both run on the Gram matrices of the state's own first chunk
 // (Theta, gate and Gram are recomputed by the real step, the Householder kernels write only
 // workspace), three times each, and the faster median is kept for the state's lifetime.
+// A chunk too small to time against launch overhead keeps the default (MFMA) kernel, and the
+// other kernel is taken only when it is clearly faster, so that the choice (and with it the
+// rounding of the results) does not follow timing noise from run to run.
+#define TUNE_MIN_ITEMS 2048
+#define TUNE_MARGIN 0.95f
 static int autotune(tn_state* s, int slot) {
     if (s->tuned) return TN_OK;
     s->tuned = 1;
@@ -741,6 +747,7 @@ static int autotune(tn_state* s, int slot) {
     const int nb = (s->L - 2) / 2 + 1;  // parity 0 bonds
     const long total = (long)s->B * nb;
     const int nitems = (int)std::min((long)s->chunk, total);
+    if (nitems < TUNE_MIN_ITEMS) return TN_OK;
     DevState ds = dev_state(s);
     DevWork w = chunk_work(s, 0, nb, slot, 0, nitems, nullptr);
     launch_update_prefix(s->prec, ds, w, s->stream);
@@ -764,7 +771,7 @@ static int autotune(tn_state* s, int slot) {
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    s->hvar = med[1] < med[0] ? 1 : 0;
+    s->hvar = med[1] < TUNE_MARGIN * med[0] ? 1 : 0;
     return TN_OK;
 }
 
