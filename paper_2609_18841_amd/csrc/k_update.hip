@@ -479,10 +479,17 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
     } else {
         const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + p);
         beta = alpha.x >= 0.0 ? -nrm : nrm;
-        const double ib = 1.0 / beta;
+        // reciprocals: hardware estimate + two Newton steps (a few ulps, shorter chain than
+        // the correctly rounded division sequence)
+        double ib = __builtin_amdgcn_rcp(beta);
+        ib = fma(fma(-beta, ib, 1.0), ib, ib);
+        ib = fma(fma(-beta, ib, 1.0), ib, ib);
         tv = mk((beta - alpha.x) * ib, -alpha.y * ib);
         const double2 z = mk(alpha.x - beta, alpha.y);
-        const double iden = 1.0 / (z.x * z.x + z.y * z.y);
+        const double den = z.x * z.x + z.y * z.y;
+        double iden = __builtin_amdgcn_rcp(den);
+        iden = fma(fma(-den, iden, 1.0), iden, iden);
+        iden = fma(fma(-den, iden, 1.0), iden, iden);
         sc = mk(z.x * iden, -z.y * iden);
     }
     const double2 v0 = (c0 > i && c0 < n) ? ((c0 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x0), sc)) : mk(0.0, 0.0);
@@ -1385,6 +1392,14 @@ __global__ __launch_bounds__(64) void k_bisect(DevState s, DevWork w) {
     }
 }
 
+// 1/x from the hardware estimate and two Newton steps: a few ulps, about half the instructions
+// of the correctly rounded division on the recurrences' dependency chains (|x| >= pivmin there)
+__device__ __forceinline__ double tv_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(fma(-x, r, 1.0), r, r);
+    return fma(fma(-x, r, 1.0), r, r);
+}
+
 template <class T>
 __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
     __shared__ double zr[VF_N * VF_K];
@@ -1418,7 +1433,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         if (fabs(dm) < pivmin) dm = -pivmin;
         zr[(n - 1) * VF_K + c] = dm;
         for (int i = n - 2; i >= 0; --i) {
-            dm = (sd[i] - lam) - se[i] * se[i] / dm;
+            dm = (sd[i] - lam) - se[i] * se[i] * tv_rcp(dm);
             if (fabs(dm) < pivmin) dm = -pivmin;
             zr[i * VF_K + c] = dm;
         }
@@ -1428,7 +1443,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         int r = 0;
         double gbest = fabs(zr[c]);
         for (int i = 1; i < n; ++i) {
-            dp = (sd[i] - lam) - se[i - 1] * se[i - 1] / dp;
+            dp = (sd[i] - lam) - se[i - 1] * se[i - 1] * tv_rcp(dp);
             if (fabs(dp) < pivmin) dp = -pivmin;
             const double gam = fabs(dp + zr[i * VF_K + c] - (sd[i] - lam));
             if (gam < gbest) {
@@ -1441,7 +1456,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         if (fabs(dp) < pivmin) dp = -pivmin;
         for (int i = 0; i < r; ++i) {
             if (i > 0) {
-                dp = (sd[i] - lam) - se[i - 1] * se[i - 1] / dp;
+                dp = (sd[i] - lam) - se[i - 1] * se[i - 1] * tv_rcp(dp);
                 if (fabs(dp) < pivmin) dp = -pivmin;
             }
             zr[i * VF_K + c] = dp;
@@ -1450,13 +1465,13 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         double zi = 1.0, nrm = 1.0;
         zr[r * VF_K + c] = 1.0;
         for (int i = r; i + 1 < n; ++i) {
-            zi = -(se[i] / zr[(i + 1) * VF_K + c]) * zi;
+            zi = -(se[i] * tv_rcp(zr[(i + 1) * VF_K + c])) * zi;
             zr[(i + 1) * VF_K + c] = zi;
             nrm += zi * zi;
         }
         zi = 1.0;
         for (int i = r - 1; i >= 0; --i) {
-            zi = -(se[i] / zr[i * VF_K + c]) * zi;
+            zi = -(se[i] * tv_rcp(zr[i * VF_K + c])) * zi;
             zr[i * VF_K + c] = zi;
             nrm += zi * zi;
         }
