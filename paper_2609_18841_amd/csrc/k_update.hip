@@ -455,19 +455,23 @@ __device__ __forceinline__ void wave_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Reflector of the (updated) row i, given as two entries per lane (columns lane, lane + 64):
-// writes v into this wave's private vector vp and returns tau; when wr, also stores d_i, e_i,
-// tau_i and v (into reflrow, the reflector's row of the reflector table).
+// Reflector of the (updated) row i, given as one entry per lane (column lane) for matrices of
+// order N = 64, two (columns lane, lane + 64) for N = 128: writes v into this wave's private
+// vector vp and returns tau; when wr, also stores d_i, e_i, tau_i and v (into reflrow, the
+// reflector's row of the reflector table).
+template <int N = HR_N>
 __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 x0, double2 x1, double2* vp,
                                                 bool wr, double* dd, double* ee, double2* tau, double2* reflrow) {
+    static_assert(N == 64 || N == 128, "one or two columns per lane");
+    constexpr bool HI = N > 64;
     const int c0 = lane, c1 = lane + 64;
     double p = 0.0;
     if (c0 >= i + 2 && c0 < n) p += x0.x * x0.x + x0.y * x0.y;
-    if (c1 >= i + 2 && c1 < n) p += x1.x * x1.x + x1.y * x1.y;
+    if (HI && c1 >= i + 2 && c1 < n) p += x1.x * x1.x + x1.y * x1.y;
     p = wave_sum_dpp(p);
     // alpha = conj(row[i+1]) and d_i = row[i] from the lanes that hold them
     const int la = (i + 1) & 63, ld = i & 63;
-    const double2 xa = (i + 1) < 64 ? x0 : x1, xd = i < 64 ? x0 : x1;
+    const double2 xa = (!HI || (i + 1) < 64) ? x0 : x1, xd = (!HI || i < 64) ? x0 : x1;
     const double2 alpha = mk(readlane_f64(xa.x, la), -readlane_f64(xa.y, la));
     const double di = readlane_f64(xd.x, ld);
     double2 tv, sc;
@@ -493,13 +497,13 @@ __device__ __forceinline__ double2 hr_reflector(int i, int n, int lane, double2 
         sc = mk(z.x * iden, -z.y * iden);
     }
     const double2 v0 = (c0 > i && c0 < n) ? ((c0 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x0), sc)) : mk(0.0, 0.0);
-    const double2 v1 = (c1 > i && c1 < n) ? ((c1 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x1), sc)) : mk(0.0, 0.0);
+    const double2 v1 = (HI && c1 > i && c1 < n) ? ((c1 == i + 1) ? mk(1.0, 0.0) : cmul(cconj(x1), sc)) : mk(0.0, 0.0);
     wave_fence();  // earlier reads of this buffer by other lanes are done
     vp[c0] = v0;
-    vp[c1] = v1;
+    if (HI) vp[c1] = v1;
     if (wr) {
         if (c0 > i && c0 < n) reflrow[c0 - i - 1] = v0;
-        if (c1 > i && c1 < n) reflrow[c1 - i - 1] = v1;
+        if (HI && c1 > i && c1 < n) reflrow[c1 - i - 1] = v1;
         if (lane == 0) {
             dd[i] = di;
             ee[i] = beta;
@@ -708,31 +712,52 @@ __device__ __forceinline__ double hm_pick(int g, double a0, double a1, double a2
     return r;
 }
 
-__global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
-    __shared__ double2 vpriv[2][HR_NW][HR_N];
-    __shared__ double2 rowold[2][HR_N];
-    __shared__ double2 ww[HR_N];
-    __shared__ double2 qpart[HR_NW];
+// The reduction in two launches.  After reflectors 0 .. K-1 and their updates, the trailing
+// block A[K:, K:] is a Hermitian matrix that the remaining reflectors reduce on their own: their
+// rows and columns all start at K or later, and the reflector of row K + i of the whole matrix
+// is reflector i of the block, entry for entry.
+//   HM_HEAD  (8 waves, n > 64 only): reflectors 0 .. K-1 with K = n - 64, then the trailing
+//            block of order 64 is written back over the Gram matrix, in place (row stride n);
+//   HM_TAIL  (4 waves): the matrix of order min(n, 64) from row and column K = max(n - 64, 0),
+//            which is the whole matrix when n <= 64.
+// The order-128 matrix fills half of a CU's registers, so the head runs one item per CU; the
+// tail holds a quarter of that and runs several, which hides the latency of its step chain.
+enum { HM_HEAD = 1, HM_TAIL = 2 };
+
+// (the tail's 122 registers leave room for four waves per SIMD: four items per CU)
+template <int NW, int PART>
+__global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevState s, DevWork w) {
+    constexpr int N = 16 * NW, NTH = 64 * NW;
+    static_assert((PART == HM_HEAD && NW == 8) || (PART == HM_TAIL && NW == 4), "head 128, tail 64");
+    __shared__ double2 vpriv[2][NW][N];
+    __shared__ double2 rowold[2][N];
+    __shared__ double2 ww[N];
+    __shared__ double2 qpart[NW];
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
-    const int n = w.gsz[j], tid = threadIdx.x;
+    const int nfull = w.gsz[j], tid = threadIdx.x;
+    if (PART == HM_HEAD && nfull <= 64) return;  // reduced whole by the tail
+    const int K0 = PART == HM_TAIL ? max(nfull - 64, 0) : 0;  // first row and column held
+    const int n = nfull - K0;                                 // order of the held matrix
+    const int ilim = PART == HM_HEAD ? nfull - 64 : n - 1;    // steps taken here
     const int wv = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, cl = lane & 15;
     const int C0 = 16 * wv, myc = C0 + cl;
-    const double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
-    double* dd = w.dd + (size_t)j * w.nmax;
-    double* ee = w.ee + (size_t)j * w.nmax;
-    double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
-    double2* tau = w.tau + (size_t)j * w.nmax;
-    hm_d4 are[8], aim[8];
+    double2* Gm = w.gram + (size_t)j * w.nmax * w.nmax;
+    const double2* G = Gm + (size_t)K0 * nfull + K0;  // row stride nfull
+    double* dd = w.dd + (size_t)j * w.nmax + K0;
+    double* ee = w.ee + (size_t)j * w.nmax + K0;
+    double2* refl = w.refl + ((size_t)j * w.nmax + K0) * w.nmax;
+    double2* tau = w.tau + (size_t)j * w.nmax + K0;
+    hm_d4 are[NW], aim[NW];
 #pragma unroll
-    for (int bi = 0; bi < 8; ++bi) {
+    for (int bi = 0; bi < NW; ++bi) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int r = 16 * bi + g + 4 * k, c = myc;
             double2 v = mk(0.0, 0.0);
-            if (r < n && c < n) v = (c <= r) ? G[(size_t)r * n + c] : cconj(G[(size_t)c * n + r]);
+            if (r < n && c < n) v = (c <= r) ? G[(size_t)r * nfull + c] : cconj(G[(size_t)c * nfull + r]);
             are[bi][k] = v.x;
             aim[bi][k] = v.y;
         }
@@ -744,16 +769,20 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
         }
         return;
     }
-    for (int e = tid; e < HR_N; e += HR_NT) ww[e] = mk(0.0, 0.0);
-    for (int e = tid; e < 2 * HR_NW * HR_N; e += HR_NT) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
+    for (int e = tid; e < N; e += NTH) ww[e] = mk(0.0, 0.0);
+    for (int e = tid; e < 2 * NW * N; e += NTH) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
     // row 0: block 0, local row 0 (g = 0, k = 0) of every wave
     if (g == 0) rowold[0][myc] = mk(are[0][0], aim[0][0]);
     __syncthreads();
     const int wlast = (n - 1) >> 4;  // owns column n-1: live at every step, writes d, e, tau, v
-    double2 tv = hr_reflector(0, n, lane, rowold[0][lane], rowold[0][lane + 64], vpriv[0][wv], wv == wlast, dd, ee,
-                              tau, refl);
+    const auto hi_half = [&](const double2* row) {
+        if constexpr (N > 64) return row[lane + 64];
+        else return mk(0.0, 0.0);
+    };
+    double2 tv = hr_reflector<N>(0, n, lane, rowold[0][lane], hi_half(rowold[0]), vpriv[0][wv], wv == wlast, dd, ee,
+                                 tau, refl);
     const bool cols_live0 = C0 < n;
-    for (int i = 0; i + 1 < n; ++i) {
+    for (int i = 0; i < ilim; ++i) {
         const double2* vc_ = vpriv[i & 1][wv];
         double2* vn_ = vpriv[(i + 1) & 1][wv];
         const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
@@ -771,7 +800,7 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
         double pr = 0.0, pim = 0.0;
         if (act && cols_live) {
 #pragma unroll
-            for (int bi = 0; bi < 8; ++bi) {
+            for (int bi = 0; bi < NW; ++bi) {
                 if (16 * bi + 15 > i && 16 * bi < n) {  // uniform
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
@@ -803,7 +832,7 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
                 const int k0 = rl >> 2;
                 double xr = 0.0, xi = 0.0;
 #pragma unroll
-                for (int bi = 0; bi < 8; ++bi)
+                for (int bi = 0; bi < NW; ++bi)
                     if (bi == bi0) {
                         xr = hm_pick(k0, are[bi][0], are[bi][1], are[bi][2], are[bi][3]);
                         xi = hm_pick(k0, aim[bi][0], aim[bi][1], aim[bi][2], aim[bi][3]);
@@ -816,7 +845,7 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
         if (act) {
             double2 q = mk(0.0, 0.0);
 #pragma unroll
-            for (int b = 0; b < HR_NW; ++b) q = cadd(q, qpart[b]);
+            for (int b = 0; b < NW; ++b) q = cadd(q, qpart[b]);
             const double2 a2t = cmul(tv, q);
             a2 = mk(-0.5 * a2t.x, -0.5 * a2t.y);
             if (g == 0) {
@@ -826,21 +855,27 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
             }
         }
         __syncthreads();  // (2)
-        // row i+1 after update i (every wave), then reflector i+1
-        double2 x0 = rowold[(i + 1) & 1][lane], x1 = rowold[(i + 1) & 1][lane + 64];
-        if (act) {
-            const double2 vr = vc_[i + 1], wr = ww[i + 1];
-            if (lane > i && lane < n) hr_rank2(x0, vr, wr, vc_[lane], ww[lane]);
-            if (lane + 64 > i && lane + 64 < n) hr_rank2(x1, vr, wr, vc_[lane + 64], ww[lane + 64]);
-        }
         double2 tvn = mk(0.0, 0.0);
-        if (i + 2 < n) {
-            tvn = hr_reflector(i + 1, n, lane, x0, x1, vn_, wv == wlast, dd, ee, tau, refl + (size_t)(i + 1) * w.nmax);
-        } else if (wv == wlast) {
-            const double2 xd = (n - 1) < 64 ? x0 : x1;
-            const double dl = readlane_f64(xd.x, (n - 1) & 63);
+        if (i + 1 < ilim) {
+            // row i+1 after update i (every wave), then reflector i+1
+            double2 x0 = rowold[(i + 1) & 1][lane], x1 = hi_half(rowold[(i + 1) & 1]);
+            if (act) {
+                const double2 vr = vc_[i + 1], wr = ww[i + 1];
+                if (lane > i && lane < n) hr_rank2(x0, vr, wr, vc_[lane], ww[lane]);
+                if constexpr (N > 64)
+                    if (lane + 64 > i && lane + 64 < n) hr_rank2(x1, vr, wr, vc_[lane + 64], ww[lane + 64]);
+            }
+            tvn = hr_reflector<N>(i + 1, n, lane, x0, x1, vn_, wv == wlast, dd, ee, tau,
+                                  refl + (size_t)(i + 1) * w.nmax);
+        } else if (PART == HM_TAIL && wv == wlast) {
+            // last diagonal entry: row n-1 after the last update
+            double2 xd = rowold[(i + 1) & 1][n - 1];
+            if (act) {
+                const double2 vr = vc_[n - 1], wr = ww[n - 1];
+                hr_rank2(xd, vr, wr, vr, wr);
+            }
             if (lane == 0) {
-                dd[n - 1] = dl;
+                dd[n - 1] = xd.x;
                 ee[n - 1] = 0.0;
             }
         }
@@ -849,7 +884,7 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
             const double2 wc = ww[myc], vc = vc_[myc];
             const double y = hm_pick(g, wc.x, wc.y, vc.x, vc.y);
 #pragma unroll
-            for (int bi = 0; bi < 8; ++bi) {
+            for (int bi = 0; bi < NW; ++bi) {
                 if (16 * bi + 15 > i && 16 * bi < n) {  // uniform
                     const double2 vr = vc_[16 * bi + cl], wr = ww[16 * bi + cl];
                     const double xre = hm_pick(g, -vr.x, -vr.y, -wr.x, -wr.y);
@@ -860,6 +895,20 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_mfma(DevState s, DevWork w) {
             }
         }
         tv = tvn;
+    }
+    if (PART == HM_HEAD) {
+        // the trailing block after update K-1, both triangles, for the tail
+        const int K = ilim;
+        if (myc >= K && myc < n) {
+#pragma unroll
+            for (int bi = 0; bi < NW; ++bi) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int r = 16 * bi + g + 4 * k;
+                    if (r >= K && r < n) Gm[(size_t)r * nfull + myc] = mk(are[bi][k], aim[bi][k]);
+                }
+            }
+        }
     }
 }
 
@@ -1768,6 +1817,12 @@ __global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned ch
 // Heavy phases hold one or two workgroups per compute unit through their register use; a caller
 // that runs two chunks on two streams can order the heavy phases of both so that light phases of
 // one chunk share the compute units with a heavy phase of the other.
+// head (order > 64 only) then tail of the MFMA Householder reduction, n <= 128
+static void launch_hetrd_mfma(const DevState& s, const DevWork& w, hipStream_t st) {
+    if (w.nmax > 64) hipLaunchKernelGGL((k_hetrd_mfma<8, HM_HEAD>), dim3(w.nitems), dim3(512), 0, st, s, w);
+    hipLaunchKernelGGL((k_hetrd_mfma<4, HM_TAIL>), dim3(w.nitems), dim3(256), 0, st, s, w);
+}
+
 template <class T>
 static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase, hipStream_t st, Prof* prof,
                                  double* glog, double* gwt) {
@@ -1797,7 +1852,7 @@ static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase,
         if (w.nmax <= HR_N && w.hvar == 1)
             hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
         else if (w.nmax <= HR_N)
-            hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+            launch_hetrd_mfma(s, w, st);
         else if (w.nmax <= HETRD_LDS_N)
             hipLaunchKernelGGL(k_hetrd<true>, dim3(w.nitems), dim3(NT), 0, st, s, w);
         else
@@ -1891,7 +1946,7 @@ void launch_hetrd_variant(const DevState& s, const DevWork& w, int variant, hipS
     if (variant == 1)
         hipLaunchKernelGGL(k_hetrd_tile, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
     else
-        hipLaunchKernelGGL(k_hetrd_mfma, dim3(w.nitems), dim3(HR_NT), 0, st, s, w);
+        launch_hetrd_mfma(s, w, st);
 }
 
 void launch_reduce_items(const DevState& s, int nb, int parity, const unsigned char* mask, const double* glog,
