@@ -1265,6 +1265,219 @@ __device__ __forceinline__ void vf_backtransform(const DevState& s, const DevWor
     }
 }
 
+// Blocked back-transformation V = Q Z on the FP64 matrix cores (256 threads, n <= 128, k <= 64).
+// Q = H_0 H_1 ... H_{n-2} is applied in blocks of 16 reflectors, the last block first, each in
+// the compact WY form H_{a0} ... H_{a0+15} = I - Y T Y^+ (Y: the block's reflectors as columns,
+// zero above their unit entries; T upper triangular with T_aa = tau_a and
+// T_{0:a, a} = -tau_a T_{0:a, 0:a} (Y_{:, 0:a}^+ y_a), the forward columnwise accumulation), so a
+// block costs Z -= Y (T (Y^+ Z)): three 16-wide products instead of 16 rank-1 passes with
+// barriers between them.  Complex products are four real 16x16x4 products (real and imaginary
+// parts apart).  The row stride BT_LD = 17 of the LDS tiles keeps transposed reads free of bank
+// conflicts.
+#define BT_LD 17
+
+// tau of reflector a0 + a for a < nr, zero for the padding columns of a short last block
+__device__ __forceinline__ double2 tau16v(const double2* tau, int a0, int a, int nr) {
+    const double2 t = tau[a0 + min(a, nr - 1)];
+    return mk(a < nr ? t.x : 0.0, a < nr ? t.y : 0.0);
+}
+
+// T factors of all blocks (they depend only on the reflectors), one wave per block: S = Y^+ Y on
+// the matrix cores with both operands read straight from the reflector table (lane l: row
+// 16 t + 4 q + l/16 of reflector a0 + l%16 is the A entry conj(.) and the B entry), then lane
+// i < 16 forms row i of T from T_ia = -tau_a sum_{m<a} T_im S_ma (T_ii = tau_i, zero left of the
+// diagonal), a chain through its own registers.  Block b is stored at tf + 256 b as nr x nr
+// (nr: its reflector count), which keeps the table within n^2 entries.  The calling wave is number
+// q of nq doing this; blocks go to the waves in snake order of their cost (block b spans
+// ntile - b row tiles).  sl: this wave's 16 x 16 scratch.
+__device__ __forceinline__ void bt_tfactors(const DevWork& w, int j, int n, int q, int nq, double2* sl,
+                                            double2* tf) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4, cl = lane & 15;
+    const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    const double2* tau = w.tau + (size_t)j * w.nmax;
+    const int nref = n - 1, nblk = (nref + 15) / 16, ntile = (n + 15) >> 4;
+    for (int b = 0; b < nblk; ++b) {
+        const int rnd = b / nq, pos = b % nq;
+        if ((rnd & 1 ? nq - 1 - pos : pos) != q) continue;  // uniform
+        const int a0 = 16 * b, nr = min(16, nref - a0);
+        const int i = a0 + cl;  // this lane's reflector
+        hm_d4 sre = {0.0, 0.0, 0.0, 0.0}, sim = {0.0, 0.0, 0.0, 0.0};
+        double2 yc[4];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+            const int r = 16 * b + 4 * q4 + g;
+            yc[q4] = (cl < nr && r > i && r < n) ? refl[(size_t)i * w.nmax + (r - i - 1)] : mk(0.0, 0.0);
+        }
+        for (int t = b; t < ntile; ++t) {
+            // the next row tile's entries load while this one's products run
+            double2 yn[4];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const int r = 16 * (t + 1) + 4 * q4 + g;
+                yn[q4] = (cl < nr && r > i && r < n) ? refl[(size_t)i * w.nmax + (r - i - 1)] : mk(0.0, 0.0);
+            }
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const double2 y = yc[q4];
+                sre = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, y.x, sre, 0, 0, 0);
+                sre = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, y.y, sre, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, y.y, sim, 0, 0, 0);
+                sim = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, y.x, sim, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) yc[q4] = yn[q4];
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sl[(g + 4 * e) * 16 + cl] = mk(sre[e], sim[e]);
+        wave_fence();
+        if (lane < 16) {
+            double2 trow[16];
+            // the reads of column a wait (through an opaque zero offset) for entry a-2: one column
+            // of reads ahead of its use, instead of all 120 hoisted to the top and spilled
+            int off = 0;
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                if (a >= 2) asm volatile("" : "+v"(off) : "v"(trow[a - 2].x));
+                double2 acc = mk(0.0, 0.0);
+#pragma unroll
+                for (int m = 0; m < a; ++m) cfma(acc, trow[m], sl[off + m * 16 + a]);
+                const double2 ta = tau16v(tau, a0, a, nr);
+                double2 v = cmul(mk(-ta.x, -ta.y), acc);
+                // plain selects (a nested choice compiles to divergent branches here)
+                v.x = a == lane ? ta.x : v.x;
+                v.y = a == lane ? ta.y : v.y;
+                v.x = a < lane ? 0.0 : v.x;
+                v.y = a < lane ? 0.0 : v.y;
+                trow[a] = v;
+            }
+            if (lane < nr) {
+#pragma unroll
+                for (int a = 0; a < 16; ++a)
+                    if (a < nr) tf[256 * b + lane * nr + a] = trow[a];
+            }
+        }
+        wave_fence();  // sl is rewritten for this wave's next block
+    }
+}
+
+// Z is held in registers as 16 x 16 tiles in the MFMA accumulator layout (lane l, element e: row
+// 16 t + l/16 + 4 e, column 16 wave + l%16).  Element e of a tile is then also the B operand (row
+// l/16, column l%16) of the 16x16x4 product over rows 16 t + 4 e .. + 3, so Y^+ Z and T W take
+// their right operand from registers; only Y and T come from LDS.  lds: (VF_N + 16) x BT_LD
+// entries (Y, then T), inside the caller's Z staging buffer once Z is in registers.
+template <class T>
+__device__ __forceinline__ void vf_backtransform_mfma(const DevState& s, const DevWork& w, const ItemDims& d, int j,
+                                                      int n, int k, const double* zr, int zs, double2* lds,
+                                                      const double2* tf) {
+    static_assert(NT == 256, "four waves, one 16-column tile of Z each");
+    double2* yl = lds;
+    double2* tt = yl + VF_N * BT_LD;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int g = lane >> 4, cl = lane & 15;
+    const int c = 16 * wv + cl;  // this lane's column of Z
+    const int ntile = (n + 15) >> 4;
+    hm_d4 zre[VF_N / 16], zim[VF_N / 16];
+#pragma unroll
+    for (int t = 0; t < VF_N / 16; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = 16 * t + g + 4 * e;
+            zre[t][e] = (c < k && r < n) ? zr[r * zs + c] : 0.0;
+            zim[t][e] = 0.0;
+        }
+    }
+    __syncthreads();  // the staging buffers alias zr
+    const double2* refl = w.refl + (size_t)j * w.nmax * w.nmax;
+    const int nref = n - 1;  // reflectors 0 .. n-2
+    const bool colive = 16 * wv < k;
+    // block b's Y entries (thread: rows r = tid % VF_N of reflectors a0 + a, a = tid / VF_N + 2 u)
+    // and T entry, loaded into registers one block ahead of their use
+    double2 ypf[16 * VF_N / NT], tpf;
+    const auto bt_load = [&](int b) {
+        const int a0 = 16 * b, nr = min(16, nref - a0);
+#pragma unroll
+        for (int u = 0; u < 16 * VF_N / NT; ++u) {
+            const int e = tid + NT * u, a = e / VF_N, r = e % VF_N, i = a0 + a;
+            ypf[u] = (a < nr && r > i && r < n) ? refl[(size_t)i * w.nmax + (r - i - 1)] : mk(0.0, 0.0);
+        }
+        const int a = tid >> 4, m = tid & 15;
+        tpf = (a < nr && m < nr) ? tf[256 * b + a * nr + m] : mk(0.0, 0.0);
+    };
+    if (nref > 0) bt_load((nref + 15) / 16 - 1);
+    for (int b = (nref + 15) / 16 - 1; b >= 0; --b) {
+#pragma unroll
+        for (int u = 0; u < 16 * VF_N / NT; ++u) {
+            const int e = tid + NT * u, a = e / VF_N, r = e % VF_N;
+            yl[r * BT_LD + a] = ypf[u];
+        }
+        tt[(tid >> 4) * BT_LD + (tid & 15)] = tpf;
+        __syncthreads();
+        if (b > 0) bt_load(b - 1);
+        if (colive) {  // uniform per wave
+            // W = Y^+ Z (16 x 16, this wave's columns): A = conj(Y[r][l%16]), B = Z[r][c]
+            hm_d4 wre = {0.0, 0.0, 0.0, 0.0}, wim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int t = 0; t < VF_N / 16; ++t) {
+                if (t >= b && t < ntile) {  // uniform
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 y = yl[(16 * t + 4 * q + g) * BT_LD + cl];
+                        const double zx = zre[t][q], zy = zim[t][q];
+                        wre = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, zx, wre, 0, 0, 0);
+                        wre = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, zy, wre, 0, 0, 0);
+                        wim = __builtin_amdgcn_mfma_f64_16x16x4f64(y.x, zy, wim, 0, 0, 0);
+                        wim = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, zx, wim, 0, 0, 0);
+                    }
+                }
+            }
+            // X = T W: A = T[l%16][4 q + l/16], B = W[4 q + l/16][l%16] = element q of W
+            hm_d4 xre = {0.0, 0.0, 0.0, 0.0}, xim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 tv = tt[cl * BT_LD + 4 * q + g];
+                xre = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.x, wre[q], xre, 0, 0, 0);
+                xre = __builtin_amdgcn_mfma_f64_16x16x4f64(-tv.y, wim[q], xre, 0, 0, 0);
+                xim = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.x, wim[q], xim, 0, 0, 0);
+                xim = __builtin_amdgcn_mfma_f64_16x16x4f64(tv.y, wre[q], xim, 0, 0, 0);
+            }
+            // Z -= Y X: A = Y[16 t + l%16][4 q + l/16], B = X[4 q + l/16][l%16] = element q of X
+#pragma unroll
+            for (int t = 0; t < VF_N / 16; ++t) {
+                if (t >= b && t < ntile) {  // uniform
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 y = yl[(16 * t + cl) * BT_LD + 4 * q + g];
+                        zre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.x, xre[q], zre[t], 0, 0, 0);
+                        zre[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(y.y, xim[q], zre[t], 0, 0, 0);
+                        zim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.x, xim[q], zim[t], 0, 0, 0);
+                        zim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-y.y, xre[q], zim[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // Y and T are rewritten for the next block
+    }
+    double2* V = w.V + (size_t)j * w.nmax * w.vld;
+    T* Br = site_ptr<T>(s, d.b, d.bond + 1);
+    // the QR route writes B_{bond+1} after expanding V, the Jacobi refinement after its sweeps
+    const bool wr_br = !(w.qr_route && d.m < d.n) && !w.jacobi;
+    if (c < k) {
+#pragma unroll
+        for (int t = 0; t < VF_N / 16; ++t) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * t + g + 4 * e;
+                if (r < n) {
+                    const double2 z = mk(zre[t][e], zim[t][e]);
+                    V[(size_t)r * w.vld + c] = z;
+                    if (wr_br) Br[(size_t)c * n + r] = cconv<T>(cconj(z));
+                }
+            }
+        }
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
     __shared__ double zr[VF_N * VF_K];
@@ -1450,11 +1663,12 @@ __device__ __forceinline__ double tv_rcp(double x) {
 }
 
 template <class T>
-__global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
-    __shared__ double zr[VF_N * VF_K];
+__global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
+    static_assert((VF_N + 16) * BT_LD * 16 <= VF_N * VF_K * 8, "back-transformation tiles fit in zr");
+    __shared__ __align__(16) double zr[VF_N * VF_K];
     __shared__ double sd[VF_N], se[VF_N];
-    __shared__ double2 vbuf[VF_N];
     __shared__ double2 part[NT];
+    __shared__ double2 slx[2][256];
     __shared__ int bad;
     ItemDims d;
     const int j = blockIdx.x;
@@ -1470,17 +1684,25 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
     }
     if (tid == 0) bad = 0;
     __syncthreads();
+    // T factors of the back-transformation blocks (waves 1..3, into the Gram slot, which the
+    // Householder reduction no longer needs) while wave 0 forms the eigenvectors of T: a wave
+    // takes as long for 16 active lanes as for 64, so one wave carries all k <= 64 columns
+    double2* tf = w.gram + (size_t)j * w.nmax * w.nmax;
+    const int wv = tid >> 6, ln = tid & 63;
+    if (wv > 0) bt_tfactors(w, j, n, wv - 1, NT / 64 - 1, wv == 1 ? part : slx[wv - 2], tf);
     double emax2 = 0.0;
+#pragma unroll 8
     for (int i = 0; i + 1 < n; ++i) emax2 = fmax(emax2, se[i] * se[i]);
     const double pivmin = DBL_MIN * fmax(1.0, emax2);
-    // column c = 16 * wave + lane (lanes 0..15 of each wavefront): four independent recurrences per CU SIMD
-    const int wv = tid >> 6, ln = tid & 63, c = 16 * wv + ln;
-    if (ln < 16 && c < k) {
+    // column c = lane of wave 0: 64 independent recurrences
+    const int c = ln;
+    if (wv == 0 && c < k) {
         const double lam = w.lsel[(size_t)j * w.nmax + c];
         // progressive (bottom-up) pivots D-_i of T - lam I, stored in the column
         double dm = sd[n - 1] - lam;
         if (fabs(dm) < pivmin) dm = -pivmin;
         zr[(n - 1) * VF_K + c] = dm;
+#pragma unroll 4
         for (int i = n - 2; i >= 0; --i) {
             dm = (sd[i] - lam) - se[i] * se[i] * tv_rcp(dm);
             if (fabs(dm) < pivmin) dm = -pivmin;
@@ -1491,6 +1713,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         if (fabs(dp) < pivmin) dp = -pivmin;
         int r = 0;
         double gbest = fabs(zr[c]);
+#pragma unroll 4
         for (int i = 1; i < n; ++i) {
             dp = (sd[i] - lam) - se[i - 1] * se[i - 1] * tv_rcp(dp);
             if (fabs(dp) < pivmin) dp = -pivmin;
@@ -1503,6 +1726,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         // D+_i for i < r replace D-_i there (D-_i is needed only below the twist)
         dp = sd[0] - lam;
         if (fabs(dp) < pivmin) dp = -pivmin;
+#pragma unroll 4
         for (int i = 0; i < r; ++i) {
             if (i > 0) {
                 dp = (sd[i] - lam) - se[i - 1] * se[i - 1] * tv_rcp(dp);
@@ -1513,12 +1737,14 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         // z_r = 1; below: z_{i+1} = -(e_i / D-_{i+1}) z_i; above: z_i = -(e_i / D+_i) z_{i+1}
         double zi = 1.0, nrm = 1.0;
         zr[r * VF_K + c] = 1.0;
+#pragma unroll 4
         for (int i = r; i + 1 < n; ++i) {
             zi = -(se[i] * tv_rcp(zr[(i + 1) * VF_K + c])) * zi;
             zr[(i + 1) * VF_K + c] = zi;
             nrm += zi * zi;
         }
         zi = 1.0;
+#pragma unroll 4
         for (int i = r - 1; i >= 0; --i) {
             zi = -(se[i] * tv_rcp(zr[i * VF_K + c])) * zi;
             zr[i * VF_K + c] = zi;
@@ -1558,7 +1784,7 @@ __global__ __launch_bounds__(NT) void k_tvecs(DevState s, DevWork w) {
         }
         __syncthreads();
     }
-    vf_backtransform<T>(s, w, d, j, n, k, zr, VF_K, vbuf, part);
+    vf_backtransform_mfma<T>(s, w, d, j, n, k, zr, VF_K, reinterpret_cast<double2*>(zr), tf);
 }
 
 // ------------------------------------------------------------------ Hastings split
