@@ -44,8 +44,9 @@ def algo_flops(n=128, m=128, chim=64, k=64, D=4):
 
 
 def profiled_traffic(kernel):
-    """HBM bytes per dispatch of `kernel` from the committed counter summary, or None when the
-    summary is missing or was taken with different kernel sources."""
+    """HBM bytes per launch of the timing bucket whose kernel is `kernel` (the sum over its template
+    instances: the Householder reduction is a head and a tail dispatch) from the committed counter
+    summary, or None when the summary is missing or was taken with different kernel sources."""
     import hashlib
     try:
         lines = open(TRAFFIC_PROFILE).read().splitlines()
@@ -59,14 +60,16 @@ def profiled_traffic(kernel):
         path = os.path.join(ROOT, "paper_2609_18841_amd", "csrc", name)
         if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] != h:
             return None
+    tot, found = 0.0, False
     for ln in lines:
         if ln.startswith("#"):
             continue
         parts = ln.split()
         nm = " ".join(parts[:-3]).replace("void ", "").split("<")[0].strip()
         if nm == kernel:
-            return float(parts[-1])
-    return None
+            tot += float(parts[-1])
+            found = True
+    return tot if found else None
 
 
 def parse():

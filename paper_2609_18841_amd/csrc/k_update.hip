@@ -712,23 +712,21 @@ __device__ __forceinline__ double hm_pick(int g, double a0, double a1, double a2
     return r;
 }
 
-// The reduction in two launches.  After reflectors 0 .. K-1 and their updates, the trailing
-// block A[K:, K:] is a Hermitian matrix that the remaining reflectors reduce on their own: their
-// rows and columns all start at K or later, and the reflector of row K + i of the whole matrix
-// is reflector i of the block, entry for entry.
-//   HM_HEAD  (8 waves, n > 64 only): reflectors 0 .. K-1 with K = n - 64, then the trailing
-//            block of order 64 is written back over the Gram matrix, in place (row stride n);
-//   HM_TAIL  (4 waves): the matrix of order min(n, 64) from row and column K = max(n - 64, 0),
-//            which is the whole matrix when n <= 64.
-// The order-128 matrix fills half of a CU's registers, so the head runs one item per CU; the
-// tail holds a quarter of that and runs several, which hides the latency of its step chain.
-enum { HM_HEAD = 1, HM_TAIL = 2 };
-
-// (the tail's 122 registers leave room for four waves per SIMD: four items per CU)
-template <int NW, int PART>
+// The reduction in stages.  After reflectors 0 .. K-1 and their updates, the trailing block
+// A[K:, K:] is a Hermitian matrix that the remaining reflectors reduce on their own: their rows
+// and columns all start at K or later, and the reflector of row K + i of the whole matrix is
+// reflector i of the block, entry for entry.  A stage k_hetrd_mfma<NW, NEXT> (NW waves) holds
+// the matrix of order min(n, 16 NW) from row and column K0 = max(n - 16 NW, 0); with NEXT > 0 it
+// takes the steps down to order NEXT and writes that trailing block back over the Gram matrix,
+// in place (row stride n), with NEXT = 0 it reduces its matrix completely.  The stages run as
+// 128 -> 64 (8 waves, one item per CU: the order-128 matrix fills half of a CU's registers) and
+// 64 -> 1 (4 waves, 122 registers: four items per CU, which hide the latency of each other's
+// step chains).  A middle stage 96 -> 64 with 6 waves at two items per CU measured slower than
+// taking those steps in the first stage.
+template <int NW, int NEXT>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevState s, DevWork w) {
     constexpr int N = 16 * NW, NTH = 64 * NW;
-    static_assert((PART == HM_HEAD && NW == 8) || (PART == HM_TAIL && NW == 4), "head 128, tail 64");
+    static_assert(NEXT < N && NEXT % 16 == 0, "a stage ends at a smaller order");
     __shared__ double2 vpriv[2][NW][N];
     __shared__ double2 rowold[2][N];
     __shared__ double2 ww[N];
@@ -737,10 +735,10 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
     const int nfull = w.gsz[j], tid = threadIdx.x;
-    if (PART == HM_HEAD && nfull <= 64) return;  // reduced whole by the tail
-    const int K0 = PART == HM_TAIL ? max(nfull - 64, 0) : 0;  // first row and column held
-    const int n = nfull - K0;                                 // order of the held matrix
-    const int ilim = PART == HM_HEAD ? nfull - 64 : n - 1;    // steps taken here
+    const int K0 = max(nfull - N, 0);                 // first row and column held
+    const int n = nfull - K0;                         // order of the held matrix
+    if (NEXT > 0 && n <= NEXT) return;                // left whole to the later stages
+    const int ilim = NEXT > 0 ? n - NEXT : n - 1;     // steps taken here
     const int wv = tid >> 6, lane = tid & 63;
     const int g = lane >> 4, cl = lane & 15;
     const int C0 = 16 * wv, myc = C0 + cl;
@@ -867,7 +865,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
             }
             tvn = hr_reflector<N>(i + 1, n, lane, x0, x1, vn_, wv == wlast, dd, ee, tau,
                                   refl + (size_t)(i + 1) * w.nmax);
-        } else if (PART == HM_TAIL && wv == wlast) {
+        } else if (NEXT == 0 && wv == wlast) {
             // last diagonal entry: row n-1 after the last update
             double2 xd = rowold[(i + 1) & 1][n - 1];
             if (act) {
@@ -896,8 +894,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
         }
         tv = tvn;
     }
-    if (PART == HM_HEAD) {
-        // the trailing block after update K-1, both triangles, for the tail
+    if (NEXT > 0) {
+        // the trailing block after update K-1, both triangles, for the next stage
         const int K = ilim;
         if (myc >= K && myc < n) {
 #pragma unroll
@@ -905,7 +903,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const int r = 16 * bi + g + 4 * k;
-                    if (r >= K && r < n) Gm[(size_t)r * nfull + myc] = mk(are[bi][k], aim[bi][k]);
+                    if (r >= K && r < n) Gm[(size_t)(K0 + r) * nfull + K0 + myc] = mk(are[bi][k], aim[bi][k]);
                 }
             }
         }
@@ -2043,10 +2041,10 @@ __global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned ch
 // Heavy phases hold one or two workgroups per compute unit through their register use; a caller
 // that runs two chunks on two streams can order the heavy phases of both so that light phases of
 // one chunk share the compute units with a heavy phase of the other.
-// head (order > 64 only) then tail of the MFMA Householder reduction, n <= 128
+// stages of the MFMA Householder reduction, n <= 128 (a stage leaves smaller items untouched)
 static void launch_hetrd_mfma(const DevState& s, const DevWork& w, hipStream_t st) {
-    if (w.nmax > 64) hipLaunchKernelGGL((k_hetrd_mfma<8, HM_HEAD>), dim3(w.nitems), dim3(512), 0, st, s, w);
-    hipLaunchKernelGGL((k_hetrd_mfma<4, HM_TAIL>), dim3(w.nitems), dim3(256), 0, st, s, w);
+    if (w.nmax > 64) hipLaunchKernelGGL((k_hetrd_mfma<8, 64>), dim3(w.nitems), dim3(512), 0, st, s, w);
+    hipLaunchKernelGGL((k_hetrd_mfma<4, 0>), dim3(w.nitems), dim3(256), 0, st, s, w);
 }
 
 template <class T>

@@ -180,3 +180,37 @@ def test_state_roundtrip_and_single_layer_on_random_state():
     C_o, _ = measure.corr_mps(st, normalize=True)
     assert _normwise(C_g, C_o) < 1e-10
     g.close()
+
+
+@pytest.mark.parametrize("chi", [40, 60])
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_uneven_orders_match_oracle(chi, prec, tol):
+    """Bond dimensions 40 and 60 at L = 14, so the Hermitian eigenproblems reach orders
+    n = 2 chi_r = 80 and 120 next to smaller ones: the two-stage Householder reduction hands
+    trailing blocks of order 64 on from orders that are not multiples of 32, and the blocked
+    back-transformation ends on a partial block of reflectors.  One first-order step on a random
+    right-isometric state; bond weights and correlations against the oracle."""
+    L = 14
+    tensors, lams, dims = tn_inputs.random_isometric_mps(11 + chi, L, chi)
+    assert max(dims) == chi
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 2, chi, tn_inputs.neel(L), precision=prec,
+                  sv_cutoff=0.0)
+    g.set_instance(0, tensors, lams, 0.0)
+    g.replicate(0)
+    mdl = M.Model(L)
+    st = tebd.TNState(tensors, lams)
+    fn = _oracle_gate_fn(mdl, "mps")
+    for parity in (0, 1):
+        tebd.apply_layer(st, {b: fn(b, 0.05) for b in M.layer_bonds(L, parity)}, parity, chi, 0.0)
+    g.tebd_step(0.05, order=1)
+    for inst in (0, 1):
+        t3, l3, ln3, _ = g.get_instance(inst)
+        err = 0.0
+        for b in range(L - 1):
+            k = min(len(l3[b]), len(st.lams[b]))
+            err = max(err, np.max(np.abs(l3[b][:k] - st.lams[b][:k])))
+        assert err < tol, (inst, err)
+        C_g, _ = measure.corr_mps(tebd.TNState(t3, l3, ln3), normalize=True)
+        C_o, _ = measure.corr_mps(st, normalize=True)
+        assert _normwise(C_g, C_o) < tol
+    g.close()
