@@ -22,6 +22,8 @@
 #include <float.h>
 
 #define NT 256
+// four doubles: one lane's share of a 16 x 16 FP64 MFMA accumulator (rows l/16 + 4 e, column l%16)
+typedef double hm_d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1)) / 2 + c; }
 
@@ -160,6 +162,99 @@ __global__ __launch_bounds__(NT) void k_gram(DevState s, DevWork w, int tiles_n)
 // separated from rounding noise.  Instead: Householder QR  Theta^+ = Q R  (Q = H_0 ... H_{m-1},
 // R m x m), the m x m Hermitian problem  R R^+ = W diag W^+  (the usual eigen pipeline), and
 // V = Q [W; 0], whose columns span the row space of Theta exactly.
+// Weighted Gram H = Theta~^+ diag(w) Theta~ for n <= 128 on the FP64 matrix cores, one item per
+// 256-thread workgroup, w_r = Lambda_{b-1}[r / d_l]^2.  The 36 lower 16 x 16 tiles of H stay in MFMA
+// accumulators: wave q owns the tile rows q and 7 - q (q + 1 and 8 - q tiles, nine per wave).
+// Slot s of a wave is the tile (q, s) for s <= q, else (7 - q, s - q - 1).  Theta~ streams through
+// LDS in chunks of 16 rows, double-buffered (the next chunk's entries load into registers during
+// the current chunk's products, so a chunk costs one barrier).  Per 4-row step, lane l supplies
+// the A operand w_r Theta~[r][16 ti + l%16] of its tile row and the B operand Theta~[r][16 tj + l%16]
+// of each tile, r = 4-row base + l/16; conj(A) B is four real 16x16x4 products.
+#define GM_RC 16
+template <class T>
+__global__ __launch_bounds__(NT, 2) void k_gram_mfma(DevState s, DevWork w) {
+    static_assert(NT == 256, "four waves, two tile rows each");
+    __shared__ T ts[2][GM_RC * 128];
+    ItemDims d;
+    const int j = blockIdx.x;
+    if (!item_dims(s, w, j, d)) return;
+    if (w.qr_route && d.m < d.n) return;  // built by k_qr_wide instead
+    const int tid = threadIdx.x;
+    if (tid == 0) w.gsz[j] = d.n;
+    const int n = d.n, m = d.m, dl = d.dl;
+    const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)j * w.theta_stride;
+    const double* lamL = (d.bond > 0 && !w.unitw) ? lam_ptr(s, d.b, d.bond - 1) : nullptr;
+    const int wv = tid >> 6, lane = tid & 63, g = lane >> 4, cl = lane & 15;
+    const int ra = wv, rb = 7 - wv;  // this wave's tile rows
+    hm_d4 gre[9], gim[9];
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+        gre[sl] = hm_d4{0.0, 0.0, 0.0, 0.0};
+        gim[sl] = hm_d4{0.0, 0.0, 0.0, 0.0};
+    }
+    const int nch = (m + GM_RC - 1) / GM_RC;
+    constexpr int PER = GM_RC * 128 / NT;  // chunk entries per thread: row e / 128, column e % 128
+    T pf[PER];
+    const auto load_chunk = [&](int ch) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + NT * u, r = ch * GM_RC + e / 128, c = e % 128;
+            pf[u] = (r < m && c < n) ? th[(size_t)r * n + c] : T{};
+        }
+    };
+    if (nch > 0) load_chunk(0);
+    for (int ch = 0; ch < nch; ++ch) {
+        T* buf = ts[ch & 1];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) buf[tid + NT * u] = pf[u];
+        __syncthreads();  // also: every wave is done with the chunk that used this buffer before
+        if (ch + 1 < nch) load_chunk(ch + 1);
+#pragma unroll
+        for (int q4 = 0; q4 < GM_RC / 4; ++q4) {
+            const int rl = 4 * q4 + g, r = ch * GM_RC + rl;
+            double wl = 1.0;
+            if (lamL && r < m) {
+                const double l = lamL[r / dl];
+                wl = l * l;
+            }
+            double2 xa = cconv<double2>(buf[rl * 128 + 16 * ra + cl]);
+            double2 xb = cconv<double2>(buf[rl * 128 + 16 * rb + cl]);
+            xa = mk(wl * xa.x, wl * xa.y);
+            xb = mk(wl * xb.x, wl * xb.y);
+#pragma unroll
+            for (int sl = 0; sl < 9; ++sl) {
+                const bool inA = sl <= ra;  // uniform per wave
+                const int ti = inA ? ra : rb, tj = inA ? sl : sl - ra - 1;
+                if (16 * ti < n) {  // uniform
+                    double ax = xa.x, ay = xa.y;
+                    ax = inA ? ax : xb.x;
+                    ay = inA ? ay : xb.y;
+                    const double2 bv = cconv<double2>(buf[rl * 128 + 16 * tj + cl]);
+                    // conj(a) b: re = ax bx + ay by, im = ax by - ay bx
+                    gre[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bv.x, gre[sl], 0, 0, 0);
+                    gre[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(ay, bv.y, gre[sl], 0, 0, 0);
+                    gim[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax, bv.y, gim[sl], 0, 0, 0);
+                    gim[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ay, bv.x, gim[sl], 0, 0, 0);
+                }
+            }
+        }
+    }
+    double2* G = w.gram + (size_t)j * w.nmax * w.nmax;
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+        const bool inA = sl <= ra;
+        const int ti = inA ? ra : rb, tj = inA ? sl : sl - ra - 1;
+        const int c = 16 * tj + cl;
+        if (16 * ti < n && c < n) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 16 * ti + g + 4 * e;
+                if (i < n) G[(size_t)i * n + c] = mk(gre[sl][e], gim[sl][e]);
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_qr_wide(DevState s, DevWork w) {
     __shared__ double red[NT / 64];
     __shared__ double2 sh_tau, sh_sc;
@@ -685,7 +780,6 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
 //   every wave forms the updated row i+1 and from it reflector i+1 (as in k_hetrd_tile);
 //   the rank-2 update A -= v w^+ + w v^+ of each live block is two MFMA 16x16x4 products
 //   (real and imaginary part) with [v_r, w_r] as the 16 x 4 operand and [w_c; v_c] as 4 x 16.
-typedef double hm_d4 __attribute__((ext_vector_type(4)));
 
 // x + (x of lane l ^ 16) and x + (x of lane l ^ 32) in the VALU: swapping a value with a copy of
 // itself across half-rows (v_permlane16_swap) or half-waves (v_permlane32_swap) leaves the lane
@@ -2041,6 +2135,19 @@ __global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned ch
 // Heavy phases hold one or two workgroups per compute unit through their register use; a caller
 // that runs two chunks on two streams can order the heavy phases of both so that light phases of
 // one chunk share the compute units with a heavy phase of the other.
+// weighted Gram matrix (and, on the QR route, the wide-Theta factorization that replaces it)
+template <class T>
+static void launch_gram(const DevState& s, const DevWork& w, hipStream_t st) {
+    if (w.nmax > 64 && w.nmax <= 128) {
+        // (for n <= 64 only the tile rows 0..3 exist and the matrix-core kernel measured slower)
+        hipLaunchKernelGGL(k_gram_mfma<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    } else {
+        const int tn = (w.nmax + 63) / 64;
+        hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+    }
+    if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
+}
+
 // stages of the MFMA Householder reduction, n <= 128 (a stage leaves smaller items untouched)
 static void launch_hetrd_mfma(const DevState& s, const DevWork& w, hipStream_t st) {
     if (w.nmax > 64) hipLaunchKernelGGL((k_hetrd_mfma<8, 64>), dim3(w.nitems), dim3(512), 0, st, s, w);
@@ -2067,8 +2174,7 @@ static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase,
         }
         prof_end(prof, TN_K_THETA, st);
         prof_begin(prof, TN_K_GRAM, st);
-        hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-        if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
+        launch_gram<T>(s, w, st);
         prof_end(prof, TN_K_GRAM, st);
         return;
     case 1:
@@ -2155,8 +2261,7 @@ static void launch_update_prefix_t(const DevState& s, const DevWork& w, hipStrea
         hipLaunchKernelGGL((k_theta_gate<T, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
     else
         hipLaunchKernelGGL((k_theta_gate<T, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
-    hipLaunchKernelGGL(k_gram<T>, dim3(tn * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-    if (w.qr_route) hipLaunchKernelGGL(k_qr_wide, dim3(w.nitems), dim3(NT), 0, st, s, w);
+    launch_gram<T>(s, w, st);
 }
 
 void launch_update_prefix(int prec, const DevState& s, const DevWork& w, hipStream_t st) {
