@@ -101,8 +101,8 @@ def qsd_noise(state, jumps, dt, rnd_row, noise_kind="gauss"):
         apply_site_op(state, site, O)
 
 
-def qsd_step(state, jumps, dt, rnd_row, gate_fn, chi_max, cutoff, noise_kind="gauss"):
-    trotter_step(state, gate_fn, 1, dt, chi_max, cutoff)
+def qsd_step(state, jumps, dt, rnd_row, gate_fn, chi_max, cutoff, noise_kind="gauss", driver="gesdd"):
+    trotter_step(state, gate_fn, 1, dt, chi_max, cutoff, driver=driver)
     qsd_noise(state, jumps, dt, rnd_row, noise_kind)
 
 

@@ -128,17 +128,18 @@ def two_site_update(state, b, G, chi_max, cutoff, driver="gesdd"):
     return w
 
 
-def apply_layer(state, gates, parity, chi_max, cutoff):
+def apply_layer(state, gates, parity, chi_max, cutoff, driver="gesdd"):
     """One Trotter layer: all bonds of one parity (they commute, Sec. 2.3)."""
     for b in layer_bonds(state.L, parity):
-        two_site_update(state, b, gates[b], chi_max, cutoff)
+        two_site_update(state, b, gates[b], chi_max, cutoff, driver=driver)
 
 
-def trotter_step(state, gate_fn, order, dt, chi_max, cutoff):
-    """One Trotter step; gate_fn(b, tau) returns the bond gate for time tau (Sec. 2.3)."""
+def trotter_step(state, gate_fn, order, dt, chi_max, cutoff, driver="gesdd"):
+    """One Trotter step; gate_fn(b, tau) returns the bond gate for time tau (Sec. 2.3).
+    driver: the LAPACK SVD routine of every two-site update (see two_site_update)."""
     for parity, tau in trotter_layers(order, dt):
         gates = {b: gate_fn(b, tau) for b in layer_bonds(state.L, parity)}
-        apply_layer(state, gates, parity, chi_max, cutoff)
+        apply_layer(state, gates, parity, chi_max, cutoff, driver=driver)
 
 
 def to_dense(state):

@@ -1013,10 +1013,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
 #define QL_TPB 32
 #define QL_LDS_N 128
 template <bool LDS>
-__global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
-    __shared__ double sdd[LDS ? QL_LDS_N * QL_TPB : 1], see[LDS ? QL_LDS_N * QL_TPB : 1];
-    const int lane = threadIdx.x;
-    const int j = blockIdx.x * QL_TPB + lane;
+__device__ __forceinline__ void steqr_item(const DevState& s, const DevWork& w, int j, int lane, double* sdd,
+                                           double* see) {
     ItemDims dm;
     if (!item_dims(s, w, j, dm)) return;
     if (w.fb && w.fb[j] != 1) return;  // eigenvectors come from the bisection path
@@ -1107,6 +1105,22 @@ __global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
         for (int i = 0; i < n; ++i) gd[i] = d[i * st];
     w.nrot[j] = nr < cap ? nr : cap;
     if (flag) atomicOr(w.flags, flag);
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
+    __shared__ double sdd[LDS ? QL_LDS_N * QL_TPB : 1], see[LDS ? QL_LDS_N * QL_TPB : 1];
+    steqr_item<LDS>(s, w, blockIdx.x * QL_TPB + threadIdx.x, threadIdx.x, sdd, see);
+}
+
+// The logged-QL pass of split mode, which only items holding a degenerate multiplet or a failed
+// twisted factorization need (usually none): a small grid scans the chunk.  One workgroup per 32
+// items would each wait for a CU slot (64 KB of LDS) behind the other stream's kernels first.
+#define QL_FB_BLOCKS 16
+__global__ __launch_bounds__(QL_TPB) void k_steqr_fb(DevState s, DevWork w) {
+    __shared__ double sdd[QL_LDS_N * QL_TPB], see[QL_LDS_N * QL_TPB];
+    for (int j = blockIdx.x * QL_TPB + threadIdx.x; j < w.nitems; j += gridDim.x * QL_TPB)
+        steqr_item<true>(s, w, j, threadIdx.x, sdd, see);
 }
 
 // ------------------------------------------------------------------ selection and truncation
@@ -2221,7 +2235,8 @@ static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase,
         return;
     default:
         if (w.fb) {
-            hipLaunchKernelGGL(k_steqr<true>, dim3((w.nitems + QL_TPB - 1) / QL_TPB), dim3(QL_TPB), 0, st, s, w);
+            const int nb = (w.nitems + QL_TPB - 1) / QL_TPB;
+            hipLaunchKernelGGL(k_steqr_fb, dim3(nb < QL_FB_BLOCKS ? nb : QL_FB_BLOCKS), dim3(QL_TPB), 0, st, s, w);
             hipLaunchKernelGGL(k_select, dim3(w.nitems), dim3(NT), 0, st, s, w, 0);
             hipLaunchKernelGGL(k_vecs_fast<T>, dim3(w.nitems), dim3(NT), 0, st, s, w);
         }

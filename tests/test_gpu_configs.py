@@ -23,7 +23,8 @@ def _normwise(a, b):
 def test_full_size_batch_sampled_against_oracle():
     """L=64, chi=64, B=1024, split precision: the benchmark's launch configuration (chunks of
     8192 two-site updates).  One trajectory is checked against the FP64 oracle on the same
-    input; every trajectory is checked for invariants."""
+    input and with the same truncation (chi, cutoff 1e-6) to the split-mode tolerance 1e-5 on
+    the correlations; every trajectory is checked for invariants."""
     L, chi, B, dt = 64, 64, 1024, 0.01
     model = api.Model.free_fermion(L)
     st = api.State(api.KIND_MPS, model, B, chi, tn_inputs.neel(L), precision=api.SPLIT, sv_cutoff=1e-6)
@@ -41,10 +42,10 @@ def test_full_size_batch_sampled_against_oracle():
     mdl = M.Model(L)
     o = tebd.TNState(t0, l0, ln0)
     fn = lambda b, tau: M.gate_heff(mdl, b, tau)  # noqa: E731
-    stochastic.qsd_step(o, mdl.jumps, dt, noise[1][inst * 4:(inst + 1) * 4], fn, chi, 1e-12)
+    stochastic.qsd_step(o, mdl.jumps, dt, noise[1][inst * 4:(inst + 1) * 4], fn, chi, 1e-6)
     C_o, n_o = measure.corr_mps(o, normalize=False)
-    assert _normwise(C_each[inst], C_o) < 1e-4
-    assert abs(nrm[inst] - n_o) / n_o < 1e-4
+    assert _normwise(C_each[inst], C_o) < 1e-5
+    assert abs(nrm[inst] - n_o) / n_o < 1e-5
     # invariants at full size
     assert np.all(np.isfinite(C_each)) and np.all(np.isfinite(nrm)) and np.all(nrm > 0)
     assert np.all(tw >= 0) and np.all(tw < 1e-2)
