@@ -175,7 +175,7 @@ def oracle_check(api, tn_inputs, st_init, L, chi, inner, dt, noise, C_gpu0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the batch on one GPU is the measured unit)"}))
         sys.exit(2)
     import torch
     import tn_inputs
