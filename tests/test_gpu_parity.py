@@ -214,3 +214,33 @@ def test_uneven_orders_match_oracle(chi, prec, tol):
         C_o, _ = measure.corr_mps(st, normalize=True)
         assert _normwise(C_g, C_o) < tol
     g.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_mpdo_orders_match_oracle(prec, tol):
+    """Local dimension 4 (vectorized density matrix) at chi = 32: the Gram orders n = 4 chi_r reach
+    128, so the split path's two-stage Householder reduction, the matrix-core Gram (row weights
+    over d_l = 4) and the blocked back-transformation run behind the 16 x 16 Liouvillian gate.
+    One first-order step on a random right-isometric tensor train; bond weights against the
+    oracle."""
+    L, chi = 8, 32
+    tensors, lams, dims = tn_inputs.random_isometric_mps(77, L, chi, d=4)
+    assert max(dims) == chi
+    g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 2, chi, tn_inputs.neel(L), precision=prec,
+                  sv_cutoff=0.0)
+    g.set_instance(0, tensors, lams, 0.0)
+    g.replicate(0)
+    mdl = M.Model(L)
+    st = tebd.TNState(tensors, lams)
+    fn = _oracle_gate_fn(mdl, "mpdo")
+    for parity in (0, 1):
+        tebd.apply_layer(st, {b: fn(b, 0.05) for b in M.layer_bonds(L, parity)}, parity, chi, 0.0)
+    g.tebd_step(0.05, order=1)
+    for inst in (0, 1):
+        _, l3, _, _ = g.get_instance(inst)
+        err = 0.0
+        for b in range(L - 1):
+            k = min(len(l3[b]), len(st.lams[b]))
+            err = max(err, np.max(np.abs(l3[b][:k] - st.lams[b][:k])))
+        assert err < tol, (inst, err)
+    g.close()
