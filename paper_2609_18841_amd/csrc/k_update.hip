@@ -821,10 +821,17 @@ template <int NW, int NEXT>
 __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevState s, DevWork w) {
     constexpr int N = 16 * NW, NTH = 64 * NW;
     static_assert(NEXT < N && NEXT % 16 == 0, "a stage ends at a smaller order");
-    __shared__ double2 vpriv[2][NW][N];
+    // SH (the four-item-per-CU tail): one wave forms each reflector into a shared vector and a
+    // third barrier per step publishes it; the waiting is covered by the other items on the CU,
+    // and three of the four waves skip the reflector arithmetic.  The head (one item per CU)
+    // keeps a private copy per wave, formed redundantly, and two barriers per step.
+    constexpr bool SH = NW == 4;
+    constexpr int NVB = SH ? 1 : NW;
+    __shared__ double2 vpriv[2][NVB][N];
     __shared__ double2 rowold[2][N];
     __shared__ double2 ww[N];
     __shared__ double2 qpart[NW];
+    __shared__ double2 tsh[2];
     ItemDims d;
     const int j = blockIdx.x;
     if (!item_dims(s, w, j, d)) return;
@@ -862,21 +869,30 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
         return;
     }
     for (int e = tid; e < N; e += NTH) ww[e] = mk(0.0, 0.0);
-    for (int e = tid; e < 2 * NW * N; e += NTH) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
+    for (int e = tid; e < 2 * NVB * N; e += NTH) (&vpriv[0][0][0])[e] = mk(0.0, 0.0);
     // row 0: block 0, local row 0 (g = 0, k = 0) of every wave
     if (g == 0) rowold[0][myc] = mk(are[0][0], aim[0][0]);
     __syncthreads();
     const int wlast = (n - 1) >> 4;  // owns column n-1: live at every step, writes d, e, tau, v
+    const int vw = SH ? 0 : wv;      // this wave's reflector buffer
     const auto hi_half = [&](const double2* row) {
         if constexpr (N > 64) return row[lane + 64];
         else return mk(0.0, 0.0);
     };
-    double2 tv = hr_reflector<N>(0, n, lane, rowold[0][lane], hi_half(rowold[0]), vpriv[0][wv], wv == wlast, dd, ee,
-                                 tau, refl);
+    double2 tv = mk(0.0, 0.0);
+    if (!SH || wv == wlast) {
+        tv = hr_reflector<N>(0, n, lane, rowold[0][lane], hi_half(rowold[0]), vpriv[0][vw], wv == wlast, dd, ee,
+                             tau, refl);
+        if (SH && lane == 0) tsh[0] = tv;
+    }
+    if (SH) {
+        __syncthreads();
+        tv = tsh[0];
+    }
     const bool cols_live0 = C0 < n;
     for (int i = 0; i < ilim; ++i) {
-        const double2* vc_ = vpriv[i & 1][wv];
-        double2* vn_ = vpriv[(i + 1) & 1][wv];
+        const double2* vc_ = vpriv[i & 1][vw];
+        double2* vn_ = vpriv[(i + 1) & 1][vw];
         const bool act = !(tv.x == 0.0 && tv.y == 0.0);  // uniform
         const bool cols_live = cols_live0 && (C0 + 15 > i);
         if (!cols_live) {
@@ -886,6 +902,7 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
             if (lane == 0) qpart[wv] = mk(0.0, 0.0);
             __syncthreads();
             __syncthreads();
+            if (SH) __syncthreads();
             continue;
         }
         // p_c = tau sum_r conj(A_rc) v_r for the wave's columns c = C0 + cl
@@ -948,8 +965,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
         }
         __syncthreads();  // (2)
         double2 tvn = mk(0.0, 0.0);
-        if (i + 1 < ilim) {
-            // row i+1 after update i (every wave), then reflector i+1
+        if (i + 1 < ilim && (!SH || wv == wlast)) {
+            // row i+1 after update i (every wave, or the owner of column n-1 alone), then reflector i+1
             double2 x0 = rowold[(i + 1) & 1][lane], x1 = hi_half(rowold[(i + 1) & 1]);
             if (act) {
                 const double2 vr = vc_[i + 1], wr = ww[i + 1];
@@ -959,7 +976,8 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
             }
             tvn = hr_reflector<N>(i + 1, n, lane, x0, x1, vn_, wv == wlast, dd, ee, tau,
                                   refl + (size_t)(i + 1) * w.nmax);
-        } else if (NEXT == 0 && wv == wlast) {
+            if (SH && lane == 0) tsh[(i + 1) & 1] = tvn;
+        } else if (NEXT == 0 && i + 1 >= ilim && wv == wlast) {
             // last diagonal entry: row n-1 after the last update
             double2 xd = rowold[(i + 1) & 1][n - 1];
             if (act) {
@@ -985,6 +1003,10 @@ __global__ __launch_bounds__(64 * NW, NW == 4 ? 4 : 2) void k_hetrd_mfma(DevStat
                     aim[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(xim, y, aim[bi], 0, 0, 0);
                 }
             }
+        }
+        if (SH) {
+            __syncthreads();  // (3) reflector i+1 and its tau are published
+            if (i + 1 < ilim) tvn = tsh[(i + 1) & 1];
         }
         tv = tvn;
     }
