@@ -205,7 +205,7 @@ static int default_chunk(int L, int B, int chi, int dmax) {
 static int default_nbm(int B, int L, int chi) {
     long per = (long)L * chi * chi;
     long cap = std::max(1L, (long)(64L * 1024 * 1024 * 4) / std::max(1L, per));
-    return (int)std::max(1L, std::min((long)B, std::min(cap, 256L)));
+    return (int)std::max(1L, std::min((long)B, std::min(cap, 1024L)));
 }
 static int log_capacity(int nmax) { return std::max(64, 4 * nmax * nmax); }
 
