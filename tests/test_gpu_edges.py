@@ -1,8 +1,9 @@
 """Edge cases of the two-site update through the C ABI, against the oracle: the largest problem
 the library accepts (chi = 256, so the Hermitian eigenproblem has n = d chi_r = 512 and takes
 the global-memory Householder / QL / eigenvector kernels), the shortest chain (L = 2, one
-bond), chi = 1 (every update truncates to a product state), and independence of an instance's
-result from the batch it sits in."""
+bond), chi = 1 (every update truncates to a product state), exactly tied singular values (the
+rainbow state, which sends split mode to its logged-QL fallback), and independence of an
+instance's result from the batch it sits in."""
 import numpy as np
 import pytest
 
@@ -124,3 +125,34 @@ def test_result_does_not_depend_on_the_batch(prec):
     for la, lb in zip(out[0][1], out[1][1]):
         assert np.array_equal(la, lb)
     assert out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("prec", [api.FP64, api.SPLIT])
+def test_exactly_degenerate_spectrum(prec):
+    """The rainbow state (site i shares a particle with site L-1-i) has flat Schmidt spectra; with
+    the identity gate (dt = 0) every kept singular value of every bond ties exactly, in complex64
+    too.  Split mode then hands every item to the logged-QL fallback for degenerate multiplets,
+    and FP64 mode meets exact ties in its Jacobi refinement.  Nothing is truncated (rank <= chi),
+    so bond weights and correlations must match the oracle run on the same input with the same
+    truncation (and the state must come back unchanged)."""
+    L, chi, cut = 8, 16, 1e-6
+    tol = 1e-10 if prec == api.FP64 else 1e-5
+    tensors, lams, dims = tn_inputs.rainbow_mps(L)
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 3, chi, tn_inputs.neel(L), precision=prec,
+                  sv_cutoff=cut)
+    g.set_instance(0, tensors, lams, 0.0)
+    g.replicate(0)
+    mdl = M.Model(L)
+    st = tebd.TNState(tensors, lams)
+    for parity in (0, 1):
+        tebd.apply_layer(st, {b: M.gate_heff(mdl, b, 0.0) for b in M.layer_bonds(L, parity)}, parity, chi, cut)
+    g.tebd_step(0.0, order=1)
+    C_o, _ = measure.corr_mps(st, normalize=True)
+    for inst in range(3):
+        t3, l3, ln3, _ = g.get_instance(inst)
+        for b in range(L - 1):
+            assert len(l3[b]) == len(st.lams[b]), (b, len(l3[b]), len(st.lams[b]))
+            assert np.max(np.abs(l3[b] - st.lams[b])) < tol
+        C_g, _ = measure.corr_mps(tebd.TNState(t3, l3, ln3), normalize=True)
+        assert np.max(np.abs(C_g - C_o)) / np.max(np.abs(C_o)) < tol
+    g.close()

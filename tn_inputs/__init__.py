@@ -56,3 +56,28 @@ def random_isometric_mps(seed, L, chi, d=2, decay=8.0):
         lam = np.exp(-np.arange(dims[b + 1]) / decay)
         lams.append(lam / np.sqrt(np.sum(lam ** 2)))
     return tensors, lams, dims
+
+
+def rainbow_mps(L):
+    """The rainbow state of an even chain: site i and site L-1-i share one particle in
+    (|01> + |10>)/sqrt(2), for every i < L/2.  Its Schmidt spectrum at bond b is flat, of rank
+    2^min(b+1, L-1-b), so every two-site block has exactly tied singular values.  Right-isometric
+    (Hastings) form with the bond index holding the occupations of the open pairs' left sites,
+    the newest in the lowest bit: site i < L/2 opens pair i, B[a, p, 2a + p] = 1/sqrt(2); site
+    j >= L/2 closes the newest pair, B[a, 1 - (a mod 2), a div 2] = 1.  Returns (tensors, lams, dims)."""
+    assert L % 2 == 0 and L >= 2
+    h = L // 2
+    dims = [1] + [2 ** min(b + 1, L - 1 - b) for b in range(L - 1)] + [1]
+    tensors = []
+    for i in range(L):
+        cl, cr = dims[i], dims[i + 1]
+        B = np.zeros((cl, 2, cr), dtype=np.complex128)
+        for a in range(cl):
+            if i < h:
+                for p in range(2):
+                    B[a, p, 2 * a + p] = 1.0 / np.sqrt(2.0)
+            else:
+                B[a, 1 - (a % 2), a // 2] = 1.0
+        tensors.append(B)
+    lams = [np.full(dims[b + 1], 1.0 / np.sqrt(dims[b + 1])) for b in range(L - 1)]
+    return tensors, lams, dims
