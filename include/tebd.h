@@ -176,8 +176,9 @@ int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 
 /* ---- autotuner -------------------------------------------------------------- */
 
-/* For n <= 128 the Householder reduction has two kernels (FP64 MFMA block columns = 0, wave
- * tiles = 1).  The first tebd_step of a state times both on the Gram matrices of its own first
+/* For n <= 128 the Householder reduction has two variants (0: FP64 MFMA block columns, run as a
+ * head launch down to order 64 and a tail launch for the rest; 1: wave tiles, one launch).  The
+ * first tebd_step of a state times both on the Gram matrices of its own first
  * chunk (median of three) when that chunk holds at least 2048 items, and takes the wave-tile
  * kernel only when it is more than 5 % faster; smaller states keep kernel 0 untimed, so the
  * choice does not follow timing noise.  tn_tuning reports the choice
@@ -226,7 +227,7 @@ int tn_schedule(void* s, int schedule);
 #define TN_K_THETA   0  /* Theta formation + gate */
 #define TN_K_GRAM    1  /* weighted Gram matrix */
 #define TN_K_HETRD   2  /* Householder tridiagonalization */
-#define TN_K_STEQR   3  /* tridiagonal QL eigenvalues + truncation rank selection */
+#define TN_K_STEQR   3  /* tridiagonal eigenvalues (QL, or bisection in split mode) + rank selection */
 #define TN_K_VECS    4  /* eigenvectors: rotations + back-transformation */
 #define TN_K_SPLIT   5  /* split / store */
 #define TN_K_MEASURE 6  /* measurement sweep */

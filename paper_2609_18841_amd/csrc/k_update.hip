@@ -5,15 +5,20 @@
 // item goes through
 //   k_theta_gate  Theta~ = G (x) (B_bond . B_{bond+1})  (complex GEMM with the gate applied to the
 //             staged output tile, eq. Theta / eq. ThetaPurified; plain k_theta for centre shifts)
-//   k_gram    H = Theta~^+ diag(Lambda_{bond-1}^2) Theta~   (FP64, lower triangle)
-//   k_hetrd   Householder reduction H = Q T Q^+, T real tridiagonal (FP64)
+//   k_gram    H = Theta~^+ diag(Lambda_{bond-1}^2) Theta~   (FP64, lower triangle; k_gram_mfma on
+//             the FP64 matrix cores for 64 < n <= 128)
+//   k_hetrd   Householder reduction H = Q T Q^+, T real tridiagonal (FP64; k_hetrd_mfma head and
+//             tail launches for n <= 128)
 //   k_steqr   implicit QL on T, logging every Givens rotation (FP64)
 //   k_select  sort eigenvalues, truncation rank, discarded weight (eq. HilbertSchmidtNorm)
 //   k_vecs    replay the rotations on the selected unit vectors, back-transform by Q,
 //             store B_{bond+1} <- V^+ (right isometry)
 //   k_split   B_bond <- Theta~ V / s  (Hastings split), dims, log s and weight per item
-// In FP64 mode every eigenvector is formed and a one-sided Jacobi refinement (k_jac_y,
-// k_jacobi, k_select mode 2, k_jac_store) replaces the last two steps.
+// In split mode with n <= 128 and chi <= 64, k_bisect (eigenvalues by Sturm counts) and k_tvecs
+// (twisted-factorization eigenvectors, blocked back-transformation on the matrix cores) replace
+// k_steqr, k_select and k_vecs; k_steqr_fb, k_select and k_vecs_fast then run only for items
+// holding a degenerate multiplet.  In FP64 mode every eigenvector is formed and a one-sided
+// Jacobi refinement (k_jac_y, k_jacobi, k_select mode 2, k_jac_store) replaces the last two steps.
 // The eigenvalues of H are the squared singular values of Theta = Lambda Theta~ and
 // its eigenvectors the right singular vectors, so this is the truncated SVD of the
 // two-site update computed in FP64 without ever forming U.
@@ -769,15 +774,16 @@ __global__ __launch_bounds__(HR_NT) void k_hetrd_tile(DevState s, DevWork w) {
     }
 }
 
-// MFMA variant for n <= 128 (512 threads = 8 waves, one item per workgroup).  Wave bj owns the
-// block column of columns 16 bj .. 16 bj + 15 over all 128 rows, held as eight 16 x 16 blocks in
-// the FP64 MFMA accumulator layout (lane l, element k: row l/16 + 4k, column l%16), real and
-// imaginary parts apart.  Per step:
+// MFMA variant for n <= 128 (k_hetrd_mfma<NW, NEXT>: NW waves, one item per workgroup, a matrix of
+// order up to 16 NW).  Wave bj owns the block column of columns 16 bj .. 16 bj + 15 over all
+// rows, held as NW 16 x 16 blocks in the FP64 MFMA accumulator layout (lane l, element k: row
+// l/16 + 4k, column l%16), real and imaginary parts apart.  Per step:
 //   p = tau A v for the wave's own 16 indices from the column sums of its blocks (A is
 //   Hermitian: p_c = sum_r conj(A_rc) v_r), i.e. per-lane products and a 4-group exchange, so p
 //   needs no exchange between waves; p^+ v is summed over waves (barrier 1);
 //   w = p - (tau/2)(p^+ v) v is published for all indices (barrier 2);
-//   every wave forms the updated row i+1 and from it reflector i+1 (as in k_hetrd_tile);
+//   the updated row i+1 and from it reflector i+1 are formed (as in k_hetrd_tile) by every wave
+//   (the 8-wave head) or by one wave and published (the 4-wave tail, barrier 3);
 //   the rank-2 update A -= v w^+ + w v^+ of each live block is two MFMA 16x16x4 products
 //   (real and imaginary part) with [v_r, w_r] as the 16 x 4 operand and [w_c; v_c] as 4 x 16.
 
