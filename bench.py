@@ -29,8 +29,25 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 # workload's launch shape (8192 / 7936 updates per dispatch); it names the sha256 of the kernel
 # sources it was taken with, and its figures are used only while the sources still match.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_qsd_B256_L64_chi64_split.txt")
-# timing bucket -> the kernel that runs in it for this workload (split precision, n = 128, chi = 64)
-BUCKET_KERNEL = {"gram": "k_gram", "hetrd": "k_hetrd_mfma", "vecs": "k_tvecs", "steqr": "k_bisect", "split": "k_split"}
+
+
+def bucket_kernel(bucket, n, chi, hetrd_variant):
+    """(kernel, bound) of a timing bucket in split precision at Gram order n and bond dimension chi:
+    the kernel that runs in it and whether its inner products sit on the matrix cores ("mfma") or
+    on the vector FP64 units ("alu").  The Gram uses the MFMA kernel for 64 < n <= 128; for
+    n <= 128 the Householder reduction is the autotuner's choice (variant 0: MFMA block columns,
+    1: vector wave tiles); the eigenvector kernel with the MFMA back-transformation runs for
+    n <= 128 and chi <= 64."""
+    if bucket == "gram":
+        return ("k_gram_mfma", "mfma") if 64 < n <= 128 else ("k_gram", "alu")
+    if bucket == "hetrd":
+        if n > 128:
+            return ("k_hetrd", "alu")
+        return ("k_hetrd_tile", "alu") if hetrd_variant == 1 else ("k_hetrd_mfma", "mfma")
+    if bucket == "vecs":
+        return ("k_tvecs", "mfma") if (n <= 128 and chi <= 64) else ("k_vecs", "alu")
+    return {"theta": ("k_theta_gate", "mfma"), "split": ("k_split", "mfma")}[bucket]
+
 
 # algorithmic FLOPs per two-site update at the workload shape (m = n = 128, chi_m = k = 64, D = 4)
 def algo_flops(n=128, m=128, chim=64, k=64, D=4):
@@ -240,8 +257,8 @@ def main():
     items_per_launch = updates / launches
     busy_s = kt[dom]["busy_ms"] / 1e3
     achieved = fl[dom] * updates / busy_s if busy_s > 0 else 0.0
-    kname = BUCKET_KERNEL.get(dom, dom)
-    roof = {"bound": "mfma" if dom in ("theta", "split") else "alu", "kernel": kname,
+    kname, bound = bucket_kernel(dom, 2 * chi, chi, st.tuning()[0])
+    roof = {"bound": bound, "kernel": kname,
             "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": profiled_traffic(kname), "traffic_unit": "bytes per launch",
             "algo_flops_per_update": fl[dom], "items_per_launch": items_per_launch,

@@ -1,0 +1,72 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract, the algorithmic work model behind the
+roofline line, and the lookup of profiled HBM traffic (summed over a timing bucket's template
+instances, and withheld once the kernel sources differ from the profiled ones)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--gpus must be 1" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_algorithmic_flops_are_the_closed_forms():
+    f = bench.algo_flops()
+    n = m = 128
+    assert f["hetrd"] == pytest.approx(16.0 / 3.0 * n ** 3)
+    assert f["gram"] == 8.0 * m * n * (n + 1) / 2
+    assert f["vecs"] == 8.0 * n * n * 64
+    assert f["split"] == 8.0 * m * n * 64
+    assert f["theta"] == 8.0 * m * n * 64 + 8.0 * 16 * 64 * 64
+
+
+def test_bucket_kernels_follow_the_dispatch():
+    # workload order n = 128, chi = 64: every update kernel contracts on the matrix cores
+    assert [bench.bucket_kernel(b, 128, 64, 0) for b in ("theta", "gram", "hetrd", "vecs", "split")] == [
+        ("k_theta_gate", "mfma"), ("k_gram_mfma", "mfma"), ("k_hetrd_mfma", "mfma"), ("k_tvecs", "mfma"),
+        ("k_split", "mfma")]
+    # the autotuner's wave-tile choice, a small order, and orders past the MFMA kernels' limits
+    assert bench.bucket_kernel("hetrd", 128, 64, 1) == ("k_hetrd_tile", "alu")
+    assert bench.bucket_kernel("gram", 64, 32, 0) == ("k_gram", "alu")
+    assert bench.bucket_kernel("hetrd", 192, 96, 0) == ("k_hetrd", "alu")
+    assert bench.bucket_kernel("vecs", 192, 96, 0) == ("k_vecs", "alu")
+
+
+def _rows(path):
+    out = {}
+    for ln in open(path).read().splitlines():
+        if ln.startswith("#") or ln.startswith("kernel ") or not ln.strip():
+            continue
+        parts = ln.split()
+        out[" ".join(parts[:-3])] = float(parts[-1])
+    return out
+
+
+def test_profiled_traffic_sums_a_buckets_dispatches(tmp_path, monkeypatch):
+    if not os.path.exists(bench.TRAFFIC_PROFILE):
+        pytest.skip("no committed traffic summary")
+    rows = _rows(bench.TRAFFIC_PROFILE)
+    hetrd = [v for k, v in rows.items() if k.replace("void ", "").split("<")[0].strip() == "k_hetrd_mfma"]
+    got = bench.profiled_traffic("k_hetrd_mfma")
+    if got is None:
+        pytest.skip("committed summary was taken with other kernel sources")
+    assert len(hetrd) == 2  # head and tail
+    assert got == pytest.approx(sum(hetrd))
+    assert bench.profiled_traffic("no_such_kernel") is None
+    # a summary whose source hash differs is not used
+    fake = tmp_path / "traffic.txt"
+    text = open(bench.TRAFFIC_PROFILE).read()
+    i = text.index("k_update.hip sha256:") + len("k_update.hip sha256:")
+    fake.write_text(text[:i] + "0" * 16 + text[i + 16:])
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake))
+    assert bench.profiled_traffic("k_hetrd_mfma") is None
