@@ -11,7 +11,8 @@ Workload (one bench step = one output interval of a quantum-state-diffusion batc
   (sigma_a ~ exp(-a/8)) at chi = 64 on every saturated bond stands in for a pre-evolved state.
 Reported: value = two-site updates/s of the batched split path (whole job), the plain
 per-instance FP64 GPU path for comparison, the roofline fraction of the dominant kernel
-(HIP events on the library stream) and the CPU oracle timed on a bounded sample.
+(HIP events on the library stream), value as a fraction of the path's flop-model bound, and the
+CPU oracle timed on a bounded sample (one core, and one process per core).
 """
 import argparse
 import json
@@ -60,6 +61,18 @@ def algo_flops(n=128, m=128, chim=64, k=64, D=4):
     }
 
 
+def path_model(d=2, chi=64):
+    """Lower-bound time model of one two-site update at bond dimension chi (local dimension d, Gram
+    order n = d chi, k = chi kept): Theta, gate and reconstruction at the FP32 matrix peak, the
+    Gram matrix (8 n^3) and a Hermitian eigensolve counted as 4 (4/3 + 2) n^3 at the FP64 peak;
+    real flops, a complex MAC counted as 8."""
+    n, k = d * chi, chi
+    f32 = 8.0 * d * d * chi ** 3 + 8.0 * (d * d) ** 2 * chi * chi + 8.0 * n * n * k
+    f64 = 8.0 * n ** 3 + 4.0 * (4.0 / 3.0 + 2.0) * n ** 3
+    t = f32 / PEAK["fp32"] + f64 / PEAK["fp64"]
+    return {"flops_per_update": f32 + f64, "t_min_us": t * 1e6, "bound_updates_per_s": 1.0 / t}
+
+
 def profiled_traffic(kernel):
     """HBM bytes per launch of the timing bucket whose kernel is `kernel` (the sum over its template
     instances: the Householder reduction is a head and a tail dispatch) from the committed counter
@@ -100,7 +113,8 @@ def parse():
     ap.add_argument("--inner", type=int, default=10, help="Trotter steps per output interval")
     ap.add_argument("--dt", type=float, default=0.01)
     ap.add_argument("--plain-instances", type=int, default=2)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-clock window of the all-core oracle run (the single-core run takes up to 6 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -133,34 +147,62 @@ def run_interval(api, st, noise, inner, dt, measure=True):
     return None
 
 
-def cpu_baseline(tn_inputs, L, chi, inner, dt, budget_s):
-    """The oracle (numpy complex128, LAPACK SVD) on one trajectory of the same workload."""
+def _oracle_qsd_run(seed, L, chi, dt, budget_s, t_start=None):
+    """Oracle QSD steps on one trajectory of the workload for budget_s seconds with BLAS limited to
+    one thread; returns (updates, t0, t1) in wall-clock seconds.  With t_start the timed loop
+    begins at that wall-clock time (the processes of the all-core run start together)."""
+    from threadpoolctl import threadpool_limits
+    import tn_inputs
     from oracle import model as M, tebd, stochastic
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    mdl = M.Model(L)
-    cache = {}
+    with threadpool_limits(limits=1):
+        mdl = M.Model(L)
+        cache = {}
 
-    def fn(b, tau):
-        if (b, tau) not in cache:
-            cache[(b, tau)] = M.gate_heff(mdl, b, tau)
-        return cache[(b, tau)]
-    tensors, lams, _ = tn_inputs.random_isometric_mps(2024, L, chi)
-    st = tebd.TNState(tensors, lams)
-    noise = tn_inputs.normals(99, (10 ** 6 // (4 * L) + 8, 4))
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s:
-        stochastic.qsd_step(st, mdl.jumps, dt, noise[steps], fn, chi, SV_CUTOFF["split"])
-        steps += 1
-    el = time.perf_counter() - t0
-    upd = steps * (L - 1)
-    return {"value": upd / el, "unit": "two-site updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} Trotter steps (+ diffusion noise) of one L={L} chi={chi} trajectory, "
-                      f"{upd} updates in {el:.1f} s, numpy complex128 + LAPACK SVD"}
+        def fn(b, tau):
+            if (b, tau) not in cache:
+                cache[(b, tau)] = M.gate_heff(mdl, b, tau)
+            return cache[(b, tau)]
+        tensors, lams, _ = tn_inputs.random_isometric_mps(2024, L, chi)
+        st = tebd.TNState(tensors, lams)
+        noise = tn_inputs.normals(seed, (10 ** 6 // (4 * L) + 8, 4))
+        if t_start is not None:
+            while time.time() < t_start:
+                time.sleep(0.002)
+        t0 = time.time()
+        steps = 0
+        while time.time() - t0 < budget_s:
+            stochastic.qsd_step(st, mdl.jumps, dt, noise[steps], fn, chi, SV_CUTOFF["split"])
+            steps += 1
+        t1 = time.time()
+    return steps * (L - 1), t0, t1
+
+
+def _oracle_qsd_job(job):
+    return _oracle_qsd_run(*job)
+
+
+def cpu_baseline(L, chi, dt, budget_s, procs=None):
+    """The oracle (numpy complex128, LAPACK SVD) on the same workload, BLAS one thread per process:
+    single-core rate (one trajectory in this process) and all-core throughput (one process per
+    core, each evolving its own trajectory, all timed over the same wall-clock window).  value is
+    the all-core throughput; cores is the number of processes, one BLAS thread each."""
+    import multiprocessing as mp
+    if procs is None:
+        procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    t_single = min(6.0, 0.5 * budget_s)
+    upd1, a, b = _oracle_qsd_run(99, L, chi, dt, t_single)
+    single = upd1 / (b - a)
+    ctx = mp.get_context("spawn")
+    t_start = time.time() + 3.0 + 0.1 * procs  # after the workers have imported numpy and scipy
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_qsd_job, [(100 + w, L, chi, dt, budget_s, t_start) for w in range(procs)])
+    upd = sum(r[0] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    return {"value": upd / wall, "unit": "two-site updates/s", "cores": procs, "kind": "oracle",
+            "single_core": {"value": single, "unit": "two-site updates/s", "updates": upd1},
+            "sample": f"{procs} processes x 1 BLAS thread, each one L={L} chi={chi} QSD trajectory of the workload "
+                      f"(numpy complex128 + LAPACK SVD), {upd} updates in a {wall:.1f} s wall-clock window; "
+                      f"single core: {upd1} updates in {b - a:.1f} s"}
 
 
 def oracle_check(api, tn_inputs, st_init, L, chi, inner, dt, noise, C_gpu0):
@@ -194,6 +236,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the batch on one GPU is the measured unit)"}))
         sys.exit(2)
+    # the oracle's CPU timing runs first, before this process touches the GPU (its worker
+    # processes start from a process without GPU state)
+    cpu = None if (args.no_cpu or args.calib_copy > 0) else cpu_baseline(args.L, args.chi, args.dt, args.cpu_seconds)
     import torch
     import tn_inputs
     from paper_2609_18841_amd import api
@@ -294,7 +339,7 @@ def main():
         err, spread = oracle_check(api, tn_inputs, init2, L, chi, inner, dt, nz, Ce[0])
         del cst
 
-    cpu = None if args.no_cpu else cpu_baseline(tn_inputs, L, chi, inner, dt, args.cpu_seconds)
+    pm = path_model(2, chi)
     res = {
         "metric": "two-site TEBD updates/sec (batched trajectories, L=64 chi=64) vs plain, at stated err",
         "value": value, "unit": "two-site updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -303,7 +348,8 @@ def main():
         "config": {"workload": f"QSD trajectory batch B={B}, L={L}, chi={chi}, dt={dt}, {inner} Trotter steps + "
                                f"noise per output, 1 measurement of C per output; split precision",
                    "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner},
-        "roofline": roof, "cpu_baseline": cpu, "plain_fp64": plain,
+        "roofline": roof, "path_roofline": dict(pm, frac=value * pm["t_min_us"] * 1e-6),
+        "cpu_baseline": cpu, "plain_fp64": plain,
         "err_vs_fp64_oracle": err, "oracle_driver_spread": spread, "kernel_ms": kt,
     }
     print(json.dumps(res))

@@ -70,3 +70,19 @@ def test_profiled_traffic_sums_a_buckets_dispatches(tmp_path, monkeypatch):
     fake.write_text(text[:i] + "0" * 16 + text[i + 16:])
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(fake))
     assert bench.profiled_traffic("k_hetrd_mfma") is None
+
+
+def test_path_model_matches_the_stated_flop_model():
+    # d = 2, chi = 64 (n = 128): Theta 8.39 MF, gate 0.52 MF, reconstruction 8.39 MF on FP32;
+    # Gram 16.8 MF and the eigensolve model 28.0 MF on FP64: about 62 MF and 0.68 us per update
+    m = bench.path_model(2, 64)
+    assert m["flops_per_update"] == pytest.approx(62.04e6, rel=1e-3)
+    assert m["t_min_us"] == pytest.approx(0.679, rel=2e-3)
+    assert m["bound_updates_per_s"] == pytest.approx(1.0 / (m["t_min_us"] * 1e-6))
+
+
+def test_cpu_baseline_runs_the_oracle_in_processes():
+    r = bench.cpu_baseline(8, 8, 0.01, 0.5, procs=2)
+    assert r["kind"] == "oracle" and r["cores"] == 2
+    assert r["value"] > 0 and r["single_core"]["value"] > 0
+    assert "2 processes x 1 BLAS thread" in r["sample"]
