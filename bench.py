@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--check-steps", type=int, default=100,
+                    help="Trotter steps of the longer oracle comparison (besides one output interval)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -205,13 +207,14 @@ def cpu_baseline(L, chi, dt, budget_s, procs=None):
                       f"single core: {upd1} updates in {b - a:.1f} s"}
 
 
-def oracle_check(api, tn_inputs, st_init, L, chi, inner, dt, noise, C_gpu0):
-    """(err, spread) for trajectory 0 after one interval, both as max |dC| / max |C|:
-    err is the GPU against the FP64 oracle on the same input and with the same truncation
-    (chi and the split state's singular-value cutoff); spread is the oracle against itself with
-    another LAPACK SVD driver (gesvd instead of gesdd).  At a binding chi the kept singular
-    vectors depend on rounding inside the SVD, and spread is the scale at which two exact FP64
-    runs already differ."""
+def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0):
+    """{steps: (err, spread)} for trajectory 0 at each checkpoint of C_gpu0 ({steps: C}), both as
+    max |dC| / max |C|: err is the GPU against the FP64 oracle on the same input and with the same
+    truncation (chi and the split state's singular-value cutoff); spread is the oracle against
+    itself with another LAPACK SVD driver (gesvd instead of gesdd).  At a binding chi the kept
+    singular vectors depend on rounding inside the SVD, and spread is the scale at which two exact
+    FP64 runs already differ."""
+    from threadpoolctl import threadpool_limits
     from oracle import model as M, tebd, stochastic, measure
     mdl = M.Model(L)
     cache = {}
@@ -221,14 +224,21 @@ def oracle_check(api, tn_inputs, st_init, L, chi, inner, dt, noise, C_gpu0):
             cache[(b, tau)] = M.gate_heff(mdl, b, tau)
         return cache[(b, tau)]
     tensors, lams = st_init
-    Cs = []
-    for driver in ("gesdd", "gesvd"):
-        st = tebd.TNState([t.copy() for t in tensors], [l.copy() for l in lams])
-        for k in range(inner):
-            stochastic.qsd_step(st, mdl.jumps, dt, noise[k][0:4], fn, chi, SV_CUTOFF["split"], driver=driver)
-        Cs.append(measure.corr_mps(st, normalize=False)[0])
-    scale = np.max(np.abs(Cs[0]))
-    return float(np.max(np.abs(C_gpu0 - Cs[0])) / scale), float(np.max(np.abs(Cs[1] - Cs[0])) / scale)
+    last = max(C_gpu0)
+    Cs = {"gesdd": {}, "gesvd": {}}
+    with threadpool_limits(limits=1):
+        for driver in Cs:
+            st = tebd.TNState([t.copy() for t in tensors], [l.copy() for l in lams])
+            for k in range(last):
+                stochastic.qsd_step(st, mdl.jumps, dt, noise[k][0:4], fn, chi, SV_CUTOFF["split"], driver=driver)
+                if k + 1 in C_gpu0:
+                    Cs[driver][k + 1] = measure.corr_mps(st, normalize=False)[0]
+    out = {}
+    for n, Cg in C_gpu0.items():
+        ref = Cs["gesdd"][n]
+        scale = np.max(np.abs(ref))
+        out[n] = (float(np.max(np.abs(Cg - ref)) / scale), float(np.max(np.abs(Cs["gesvd"][n] - ref)) / scale))
+    return out
 
 
 def main():
@@ -331,12 +341,21 @@ def main():
         del pst
         torch.cuda.empty_cache()
 
+    checks = None
     if not args.no_check:
+        # trajectory 0 of a two-trajectory batch against the oracle after one output interval and
+        # after check_steps Trotter steps, on the same noise
         cst, init2 = make_state(api, tn_inputs, api.SPLIT, 2, L, chi)
-        nz = tn_inputs.normals(7, (inner, B * 2 * 2))[:, :2 * 2 * 2]
-        run_interval(api, cst, nz, inner, dt, measure=False)
-        _, _, Ce, _ = cst.measure_corr(normalize=0, each=True)
-        err, spread = oracle_check(api, tn_inputs, init2, L, chi, inner, dt, nz, Ce[0])
+        nlong = max(inner, args.check_steps)
+        nz = tn_inputs.normals(7, (nlong, B * 2 * 2))[:, :2 * 2 * 2]
+        Cg = {}
+        for k in range(nlong):
+            cst.tebd_step(dt, order=1)
+            cst.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
+            if k + 1 in (inner, nlong):
+                Cg[k + 1] = cst.measure_corr(normalize=0, each=True)[2][0]
+        checks = oracle_check(tn_inputs, init2, L, chi, dt, nz, Cg)
+        err, spread = checks[inner]
         del cst
 
     pm = path_model(2, chi)
@@ -350,7 +369,10 @@ def main():
                    "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner},
         "roofline": roof, "path_roofline": dict(pm, frac=value * pm["t_min_us"] * 1e-6),
         "cpu_baseline": cpu, "plain_fp64": plain,
-        "err_vs_fp64_oracle": err, "oracle_driver_spread": spread, "kernel_ms": kt,
+        "err_vs_fp64_oracle": err, "oracle_driver_spread": spread,
+        "err_by_steps": None if checks is None else {str(n): {"err_vs_fp64_oracle": e, "oracle_driver_spread": sp}
+                                                      for n, (e, sp) in sorted(checks.items())},
+        "kernel_ms": kt,
     }
     print(json.dumps(res))
 

@@ -86,3 +86,29 @@ def test_cpu_baseline_runs_the_oracle_in_processes():
     assert r["kind"] == "oracle" and r["cores"] == 2
     assert r["value"] > 0 and r["single_core"]["value"] > 0
     assert "2 processes x 1 BLAS thread" in r["sample"]
+
+
+def test_oracle_check_reports_each_checkpoint():
+    # the oracle's own gesdd run, handed in as the device result, has no error; the other LAPACK
+    # driver differs from it only by rounding
+    import numpy as np
+    import tn_inputs
+    from oracle import model as M, tebd, stochastic, measure
+    L, chi, dt = 8, 8, 0.01
+    tensors, lams, _ = tn_inputs.random_isometric_mps(2024, L, chi)
+    nz = tn_inputs.normals(7, (5, 8))
+    mdl = M.Model(L)
+    st = tebd.TNState([t.copy() for t in tensors], [l.copy() for l in lams])
+    C = {}
+    for k in range(5):
+        stochastic.qsd_step(st, mdl.jumps, dt, nz[k][0:4], lambda b, tau: M.gate_heff(mdl, b, tau), chi,
+                            bench.SV_CUTOFF["split"], driver="gesdd")
+        if k + 1 in (2, 5):
+            C[k + 1] = measure.corr_mps(st, normalize=False)[0]
+    out = bench.oracle_check(tn_inputs, (tensors, lams), L, chi, dt, nz, C)
+    assert sorted(out) == [2, 5]
+    for err, spread in out.values():
+        assert err == 0.0
+        assert spread < 1e-12
+    out = bench.oracle_check(tn_inputs, (tensors, lams), L, chi, dt, nz, {5: C[5] + 1e-3 * np.abs(C[5]).max()})
+    assert abs(out[5][0] - 1e-3) < 1e-9
