@@ -22,7 +22,8 @@ dense      exact Trotter products on the full state vector / density vector
 tebd       Hastings-form TEBD two-site update + layer schedule (Sec. 2.3, 3.1,
            3.2, 4)
 sweep      the paper's sequential mixed-canonical sweep (Sec. 2.3, eq. ShiftCenter)
-stochastic quantum-trajectory and quantum-state-diffusion steps (Sec. 4.1, 4.2)
+stochastic quantum-trajectory and quantum-state-diffusion steps, and the batch estimators
+           of the linear unravelling (Sec. 4.1, 4.2)
 kraus      Kraus-index compression of the locally purified form (Sec. 3.2)
 measure    <c_i^+ c_j> by exact (gauge-independent) contraction
 """

@@ -30,7 +30,7 @@ All l_k of a step are taken from the same state, before any of the step's factor
 """
 import numpy as np
 
-from .measure import jump_expectations, local_expectations
+from .measure import corr_mps, jump_expectations, local_expectations
 from .tebd import trotter_step
 
 
@@ -163,3 +163,18 @@ def qsd_noise_shifted(state, jumps, dt, rnd_row, noise_kind="gauss"):
 def qsd_step_shifted(state, jumps, dt, rnd_row, gate_fn, chi_max, cutoff, noise_kind="gauss"):
     trotter_step(state, gate_fn, 1, dt, chi_max, cutoff)
     qsd_noise_shifted(state, jumps, dt, rnd_row, noise_kind)
+
+
+def qsd_estimators(states):
+    """Batch estimators of the linear unravelling (Sec. 4.2): the histories are never
+    renormalized, so <psi|psi> fluctuates around 1.  Returns (mean, ratio, mean_norm):
+      mean  = (1/B) sum_b <psi_b|O|psi_b>, the estimator of the paper;
+      ratio = sum_b <psi_b|O|psi_b> / sum_b <psi_b|psi_b>, which divides out the norm
+              fluctuation of the sample;
+      mean_norm = (1/B) sum_b <psi_b|psi_b>, whose expectation is 1.
+    O runs over the c_i^+ c_j of the correlation matrix."""
+    pairs = [corr_mps(st, normalize=False) for st in states]
+    C_sum = sum(C for C, _ in pairs)
+    n_sum = sum(n for _, n in pairs)
+    B = len(states)
+    return C_sum / B, C_sum / n_sum, n_sum / B

@@ -313,6 +313,36 @@ def test_trajectory_average_matches_exact_within_clt(kind):
         assert abs(norms.mean() - 1) < 4 * norms.std(ddof=1) / np.sqrt(ntraj) + 0.02
 
 
+def test_qsd_ratio_estimator_is_the_norm_weighted_average():
+    """Sec. 4.2 (linear unravelling, histories not renormalized): the ratio estimator
+    sum <psi|O|psi> / sum <psi|psi> is the average of the normalized expectations weighted by
+    each history's norm; for one history it is that history's normalized C, and the mean norm
+    is the plain contraction <psi|psi> with the carried scale."""
+    L, chi, dt, nsteps, B = 6, 8, 0.02, 12, 5
+    mdl = M.Model(L)
+    fn = lambda b, tau: M.gate_heff(mdl, b, tau)  # noqa: E731
+    rng = np.random.default_rng(5)
+    states = []
+    for _ in range(B):
+        st = tebd.product_state([1, 0] * (L // 2), "mps")
+        rn = rng.standard_normal((nsteps, 4))
+        for k in range(nsteps):
+            stochastic.qsd_step(st, mdl.jumps, dt, rn[k], fn, chi, 1e-12)
+        states.append(st)
+    mean, ratio, mnorm = stochastic.qsd_estimators(states)
+    norms = np.array([measure.norm2(st) for st in states])
+    assert np.std(norms) > 1e-3  # the histories' norms differ, so the two estimators differ
+    Cn = [measure.corr_mps(st, normalize=True)[0] for st in states]
+    weighted = sum(n * C for n, C in zip(norms, Cn)) / norms.sum()
+    assert np.max(np.abs(ratio - weighted)) < 1e-12
+    assert abs(mnorm - norms.mean()) < 1e-12
+    assert np.max(np.abs(mean - sum(n * C for n, C in zip(norms, Cn)) / B)) < 1e-12
+    assert np.max(np.abs(mean - ratio)) > 1e-6
+    m1, r1, n1 = stochastic.qsd_estimators(states[:1])
+    assert np.max(np.abs(r1 - Cn[0])) < 1e-12
+    assert np.max(np.abs(m1 - norms[0] * Cn[0])) < 1e-12 and abs(n1 - norms[0]) < 1e-12
+
+
 def test_kraus_thin_route_equals_full_diagonalization():
     """Sec. 3.2, eq. MatrixR / eq. NewPurified with the gamma dt factor: the 2chi_k x 2chi_k Gram
     route gives the same sum_k A A^+ as diagonalizing the full R."""
