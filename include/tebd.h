@@ -133,7 +133,9 @@ int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
 
 /* Correlation matrix C_ij = <c_i^+ c_j> (Sec. 2.1) with the Jordan-Wigner string,
  * by exact contraction of each instance.
- * normalize (MPS): 1 -> <psi|O|psi>/<psi|psi>; 0 -> <psi|O|psi> (linear QSD estimator).
+ * normalize (MPS): 1 -> <psi|O|psi>/<psi|psi>; 0 -> <psi|O|psi> (the linear QSD estimator of
+ * Sec. 4.2, histories not renormalized); 2 -> as 0 per instance (C_each, C_var), but C_mean is
+ * the ratio sum_b <psi_b|O|psi_b> / sum_b <psi_b|psi_b>; any other nonzero value acts as 1.
  * MPDO: Tr(rho O)/Tr rho; PURIFIED: Tr(X X^+ O)/Tr(X X^+) (normalize ignored).
  * C_mean: L*L complex, batch mean (row i = c_i^+).  C_var: L*L doubles or NULL, batch
  * variance E|C - mean|^2.  C_each: B*L*L complex or NULL.  norm_out: B doubles or

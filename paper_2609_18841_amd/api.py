@@ -159,6 +159,9 @@ class State:
         return jumped, mask
 
     def measure_corr(self, normalize=1, each=False):
+        """(C_mean, C_var, C_each or None, norms).  normalize on an MPS: 1 normalized per
+        instance, 0 the linear QSD values <psi|O|psi>, 2 the same per instance with C_mean the
+        ratio sum <psi|O|psi> / sum <psi|psi>."""
         L = self.L
         mean = np.zeros((L, L), dtype=np.complex128)
         var = np.zeros((L, L))

@@ -872,19 +872,25 @@ __global__ void k_meas_scale(DevState s, double2* Ceach, double* nrm, int mode) 
         else nrm[b] = n * exp(2.0 * s.lognorm[b]);
     }
 }
-// batch mean and variance per entry (fixed summation order)
-__global__ void k_meas_stats(int B, int LL, const double2* Ceach, double2* mean, double* var) {
+// batch mean and variance per entry (fixed summation order); with ratio the mean entry is
+// sum_b C_b / sum_b <psi_b|psi_b> (the variance stays that of the per-instance values)
+__global__ void k_meas_stats(int B, int LL, const double2* Ceach, const double* nrm, int ratio, double2* mean,
+                             double* var) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= LL) return;
     double2 m = mk(0, 0);
     for (int b = 0; b < B; ++b) m = cadd(m, Ceach[(size_t)b * LL + e]);
+    double nsum = 0.0;
+    if (ratio)
+        for (int b = 0; b < B; ++b) nsum += nrm[b];
+    const double2 csum = m;
     m = cscale(m, 1.0 / B);
     double v = 0.0;
     for (int b = 0; b < B; ++b) {
         double2 d = csub(Ceach[(size_t)b * LL + e], m);
         v += d.x * d.x + d.y * d.y;
     }
-    mean[e] = m;
+    mean[e] = ratio ? cscale(csum, 1.0 / nsum) : m;
     var[e] = B > 1 ? v / (B - 1) : 0.0;
 }
 
@@ -902,12 +908,16 @@ extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_va
         else launch_measure_mps(s->prec, ds, mw, s->stream);
         HIPCHK(hipGetLastError());
     }
-    int mode = s->kind == TN_KIND_MPDO ? 2 : ((s->kind == TN_KIND_MPS && !normalize) ? 1 : 0);
+    // normalize 0 and 2 on an MPS keep <psi|O|psi> per instance (linear QSD); 2 also divides the
+    // batch sum by the summed norms
+    const bool linear = s->kind == TN_KIND_MPS && (normalize == 0 || normalize == 2);
+    const int ratio = s->kind == TN_KIND_MPS && normalize == 2;
+    int mode = s->kind == TN_KIND_MPDO ? 2 : (linear ? 1 : 0);
     double2* ce = at<double2>(s, s->lay.off_ceach);
     double* nr = at<double>(s, s->lay.off_nrm);
     hipLaunchKernelGGL(k_meas_scale, dim3(s->B), dim3(256), 0, s->stream, ds, ce, nr, mode);
     const int LL = s->L * s->L;
-    hipLaunchKernelGGL(k_meas_stats, dim3((LL + 255) / 256), dim3(256), 0, s->stream, s->B, LL, ce,
+    hipLaunchKernelGGL(k_meas_stats, dim3((LL + 255) / 256), dim3(256), 0, s->stream, s->B, LL, ce, nr, ratio,
                        at<double2>(s, s->lay.off_cmean), at<double>(s, s->lay.off_cvar));
     HIPCHK(hipGetLastError());
     prof_end(&s->prof, TN_K_MEASURE, s->stream);

@@ -101,6 +101,37 @@ def test_qsd_batch_matches_oracle_per_trajectory():
     g.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_qsd_batch_estimators_match_oracle(prec, tol):
+    """Sec. 4.2, linear unravelling: the batch mean of <psi|O|psi>, the ratio estimator
+    sum <psi|O|psi> / sum <psi|psi> (normalize 2) and the mean norm against the oracle's."""
+    L, chi, dt, nsteps, B = 6, 8, 0.05, 20, 6  # the histories' norms spread over 0.9 .. 1.8
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    noise = tn_inputs.normals(321, (nsteps, B, 2, 2))
+    fn = _oracle_gate_fn(mdl, "mps")
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ, precision=prec)
+    for k in range(nsteps):
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_QSD, dt, noise[k].reshape(-1), api.NOISE_GAUSS)
+    C_lin, var0, each0, n0 = g.measure_corr(normalize=0, each=True)
+    C_rat, var2, each2, n2 = g.measure_corr(normalize=2, each=True)
+    g.close()
+    states = []
+    for b in range(B):
+        st = tebd.product_state(occ, "mps")
+        for k in range(nsteps):
+            stochastic.qsd_step(st, mdl.jumps, dt, noise[k, b].reshape(-1), fn, chi, 1e-12)
+        states.append(st)
+    mean_o, ratio_o, mnorm_o = stochastic.qsd_estimators(states)
+    assert _normwise(C_lin, mean_o) < tol
+    assert _normwise(C_rat, ratio_o) < tol
+    assert abs(n2.mean() - mnorm_o) / mnorm_o < tol
+    # per instance, mode 2 returns the linear values of mode 0
+    assert np.array_equal(each0, each2) and np.array_equal(n0, n2) and np.array_equal(var0, var2)
+    assert _normwise(C_rat, C_lin) > 0.1  # the two estimators differ by 17 % at this sample
+
+
 def test_qt_batch_matches_oracle_jump_by_jump():
     L, chi, dt, nsteps, B = 6, 8, 0.05, 12, 6
     occ = tn_inputs.neel(L)
