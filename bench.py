@@ -183,6 +183,22 @@ def _oracle_qsd_job(job):
     return _oracle_qsd_run(*job)
 
 
+def _host_info():
+    """CPU model, logical CPUs (all, and those this process may run on) and numpy's BLAS/LAPACK."""
+    info = {"cpu_model": None, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            info["cpu_model"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    try:
+        deps = np.show_config(mode="dicts").get("Build Dependencies", {})
+        info["numpy_blas"] = {k: f"{v.get('name')} {v.get('version')}" for k, v in deps.items()}
+    except Exception:
+        info["numpy_blas"] = None
+    return info
+
+
 def cpu_baseline(L, chi, dt, budget_s, procs=None):
     """The oracle (numpy complex128, LAPACK SVD) on the same workload, BLAS one thread per process:
     single-core rate (one trajectory in this process) and all-core throughput (one process per
@@ -202,18 +218,20 @@ def cpu_baseline(L, chi, dt, budget_s, procs=None):
     wall = max(r[2] for r in res) - min(r[1] for r in res)
     return {"value": upd / wall, "unit": "two-site updates/s", "cores": procs, "kind": "oracle",
             "single_core": {"value": single, "unit": "two-site updates/s", "updates": upd1},
+            "host": _host_info(),
             "sample": f"{procs} processes x 1 BLAS thread, each one L={L} chi={chi} QSD trajectory of the workload "
                       f"(numpy complex128 + LAPACK SVD), {upd} updates in a {wall:.1f} s wall-clock window; "
                       f"single core: {upd1} updates in {b - a:.1f} s"}
 
 
 def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0):
-    """{steps: (err, spread)} for trajectory 0 at each checkpoint of C_gpu0 ({steps: C}), both as
-    max |dC| / max |C|: err is the GPU against the FP64 oracle on the same input and with the same
-    truncation (chi and the split state's singular-value cutoff); spread is the oracle against
-    itself with another LAPACK SVD driver (gesvd instead of gesdd).  At a binding chi the kept
-    singular vectors depend on rounding inside the SVD, and spread is the scale at which two exact
-    FP64 runs already differ."""
+    """{steps: (err, spread, err_density, err_nn)} for trajectory 0 at each checkpoint of C_gpu0
+    ({steps: C}).  err and spread are max |dC| / max |C|: err is the GPU against the FP64 oracle on
+    the same input and with the same truncation (chi and the split state's singular-value cutoff);
+    spread is the oracle against itself with another LAPACK SVD driver (gesvd instead of gesdd).
+    At a binding chi the kept singular vectors depend on rounding inside the SVD, and spread is the
+    scale at which two exact FP64 runs already differ.  err_density and err_nn are the GPU's
+    elementwise relative errors on the diagonal (densities) and on the first off-diagonal."""
     from threadpoolctl import threadpool_limits
     from oracle import model as M, tebd, stochastic, measure
     mdl = M.Model(L)
@@ -237,8 +255,14 @@ def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0):
     for n, Cg in C_gpu0.items():
         ref = Cs["gesdd"][n]
         scale = np.max(np.abs(ref))
-        out[n] = (float(np.max(np.abs(Cg - ref)) / scale), float(np.max(np.abs(Cs["gesvd"][n] - ref)) / scale))
+        out[n] = (float(np.max(np.abs(Cg - ref)) / scale), float(np.max(np.abs(Cs["gesvd"][n] - ref)) / scale),
+                  _elementwise(np.diag(Cg), np.diag(ref)), _elementwise(np.diag(Cg, 1), np.diag(ref, 1)))
     return out
+
+
+def _elementwise(a, b):
+    """max_i |a_i - b_i| / |b_i| (the densities C_ii, or the nearest-neighbour terms C_i,i+1)."""
+    return float(np.max(np.abs(a - b) / np.abs(b)))
 
 
 def main():
@@ -355,7 +379,7 @@ def main():
             if k + 1 in (inner, nlong):
                 Cg[k + 1] = cst.measure_corr(normalize=0, each=True)[2][0]
         checks = oracle_check(tn_inputs, init2, L, chi, dt, nz, Cg)
-        err, spread = checks[inner]
+        err, spread = checks[inner][:2]
         del cst
 
     pm = path_model(2, chi)
@@ -370,8 +394,9 @@ def main():
         "roofline": roof, "path_roofline": dict(pm, frac=value * pm["t_min_us"] * 1e-6),
         "cpu_baseline": cpu, "plain_fp64": plain,
         "err_vs_fp64_oracle": err, "oracle_driver_spread": spread,
-        "err_by_steps": None if checks is None else {str(n): {"err_vs_fp64_oracle": e, "oracle_driver_spread": sp}
-                                                      for n, (e, sp) in sorted(checks.items())},
+        "err_by_steps": None if checks is None else {
+            str(n): {"err_vs_fp64_oracle": e, "oracle_driver_spread": sp, "density_elementwise": ed,
+                     "nearest_neighbour_elementwise": en} for n, (e, sp, ed, en) in sorted(checks.items())},
         "kernel_ms": kt,
     }
     print(json.dumps(res))

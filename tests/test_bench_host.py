@@ -86,6 +86,7 @@ def test_cpu_baseline_runs_the_oracle_in_processes():
     assert r["kind"] == "oracle" and r["cores"] == 2
     assert r["value"] > 0 and r["single_core"]["value"] > 0
     assert "2 processes x 1 BLAS thread" in r["sample"]
+    assert r["host"]["nproc"] >= 1 and r["host"]["affinity"] >= 1
 
 
 def test_oracle_check_reports_each_checkpoint():
@@ -107,8 +108,8 @@ def test_oracle_check_reports_each_checkpoint():
             C[k + 1] = measure.corr_mps(st, normalize=False)[0]
     out = bench.oracle_check(tn_inputs, (tensors, lams), L, chi, dt, nz, C)
     assert sorted(out) == [2, 5]
-    for err, spread in out.values():
-        assert err == 0.0
+    for err, spread, e_diag, e_nn in out.values():
+        assert err == 0.0 and e_diag == 0.0 and e_nn == 0.0
         assert spread < 1e-12
     out = bench.oracle_check(tn_inputs, (tensors, lams), L, chi, dt, nz, {5: C[5] + 1e-3 * np.abs(C[5]).max()})
     assert abs(out[5][0] - 1e-3) < 1e-9
