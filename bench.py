@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--overlap-measure", action="store_true",
+                    help="measure each output from a snapshot, beside the next interval's steps")
     ap.add_argument("--check-steps", type=int, default=100,
                     help="Trotter steps of the longer oracle comparison (besides one output interval)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -298,19 +300,36 @@ def main():
           flush=True)
 
     err = spread = None
+    overlap = args.overlap_measure
+    if overlap:
+        st.measure_async_enable()
+
+    def interval(i0, pending):
+        # the steps of one output interval, then its measurement: with overlap the measurement of
+        # a snapshot runs beside the next interval's steps and is collected before the next start
+        run_interval(api, st, noise[i0:i0 + inner], inner, dt, measure=not overlap)
+        if overlap:
+            if pending:
+                st.measure_finish()
+            st.measure_start(0)
+        return overlap
+
+    pending = False
     for w in range(args.warmup):
-        out = run_interval(api, st, noise[w * inner:(w + 1) * inner], inner, dt, measure=True)
-        if w == 0 and not args.no_check:
-            _, _, _, _ = out
+        pending = interval(w * inner, pending)
         print(f"# warmup {w} done", file=sys.stderr, flush=True)
+    if pending:
+        st.measure_finish()
+        pending = False
 
     torch.cuda.synchronize()
     st.prof_enable(True)
     t0 = time.perf_counter()
     for s in range(args.steps):
-        i0 = (args.warmup + s) * inner
-        run_interval(api, st, noise[i0:i0 + inner], inner, dt, measure=True)
+        pending = interval((args.warmup + s) * inner, pending)
         print(f"# step {s} done", file=sys.stderr, flush=True)
+    if pending:
+        st.measure_finish()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     updates = args.steps * inner * (L - 1) * B
@@ -390,7 +409,8 @@ def main():
         "dtype": "c64-contract/f64-svd", "data": "synthetic",
         "config": {"workload": f"QSD trajectory batch B={B}, L={L}, chi={chi}, dt={dt}, {inner} Trotter steps + "
                                f"noise per output, 1 measurement of C per output; split precision",
-                   "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner},
+                   "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner,
+                   "measurement": "beside the next interval's steps (snapshot)" if overlap else "synchronous"},
         "roofline": roof, "path_roofline": dict(pm, frac=value * pm["t_min_us"] * 1e-6),
         "cpu_baseline": cpu, "plain_fp64": plain,
         "err_vs_fp64_oracle": err, "oracle_driver_spread": spread,

@@ -143,6 +143,30 @@ int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
 int measure_corr(void* s, int normalize, double* C_mean, double* C_var, double* C_each,
                  double* norm_out);
 
+/* ---- asynchronous measurement -------------------------------------------- */
+
+/* The same measurement as measure_corr, overlapped with the steps that follow it.
+ * tn_measure_async_bytes: size of a second caller-owned device buffer (256-byte aligned) that
+ *   holds a snapshot of the state (tensors, bond weights, dims, log-norms), the measurement's own
+ *   workspace and its outputs; 0 for a null handle.
+ * tn_measure_async_enable: hand that buffer to the state (the library neither frees nor resizes
+ *   it) and create the library's measurement stream (default priority).  TN_ENOMEM if bytes is
+ *   below tn_measure_async_bytes, TN_EINVAL on a null or misaligned buffer or while a
+ *   measurement is outstanding.
+ * measure_corr_start: copy the state, in the order of the work queued on the state's stream,
+ *   into the snapshot and launch the measurement of the snapshot on the measurement stream;
+ *   returns without waiting.  Later tebd_step / apply_jumps calls evolve the live state
+ *   meanwhile.  normalize as for measure_corr.  At most one measurement is outstanding:
+ *   TN_EINVAL if one is, or if the buffer was never given.
+ * measure_corr_finish: wait for the outstanding measurement and copy its results out, with the
+ *   meaning and layout of measure_corr's outputs (C_mean required, the others may be NULL);
+ *   TN_EINVAL if none is outstanding.  The results equal those measure_corr would have
+ *   returned at the time of measure_corr_start, bit for bit. */
+size_t tn_measure_async_bytes(const void* s);
+int tn_measure_async_enable(void* s, void* buf, size_t bytes);
+int measure_corr_start(void* s, int normalize);
+int measure_corr_finish(void* s, double* C_mean, double* C_var, double* C_each, double* norm_out);
+
 /* Release the handle (not the arena). */
 int mps_free(void* s);
 

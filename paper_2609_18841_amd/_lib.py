@@ -10,7 +10,8 @@ EXPORTS = [
     "mps_arena_bytes", "mps_alloc", "tebd_step", "apply_jumps", "measure_corr", "mps_free",
     "mps_last_error", "mps_instance_tensor_capacity", "mps_instance_lambda_capacity",
     "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_overlap", "tn_schedule", "tn_prof_enable",
-    "tn_prof_query", "tn_prof_busy",
+    "tn_prof_query", "tn_prof_busy", "tn_measure_async_bytes", "tn_measure_async_enable", "measure_corr_start",
+    "measure_corr_finish",
 ]
 
 
@@ -50,6 +51,14 @@ def load():
     lib.apply_jumps.argtypes = [vp, ctypes.c_int, ctypes.c_double, dp, ctypes.c_int, ip, ubp]
     lib.measure_corr.restype = ctypes.c_int
     lib.measure_corr.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp]
+    lib.tn_measure_async_bytes.restype = sz
+    lib.tn_measure_async_bytes.argtypes = [vp]
+    lib.tn_measure_async_enable.restype = ctypes.c_int
+    lib.tn_measure_async_enable.argtypes = [vp, vp, sz]
+    lib.measure_corr_start.restype = ctypes.c_int
+    lib.measure_corr_start.argtypes = [vp, ctypes.c_int]
+    lib.measure_corr_finish.restype = ctypes.c_int
+    lib.measure_corr_finish.argtypes = [vp, dp, dp, dp, dp]
     lib.mps_free.restype = ctypes.c_int
     lib.mps_free.argtypes = [vp]
     lib.mps_last_error.restype = ctypes.c_char_p

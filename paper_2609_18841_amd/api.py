@@ -171,6 +171,29 @@ class State:
                                      _dp(ce.view(np.float64)) if each else None, _dp(nrm)))
         return mean, var, ce, nrm
 
+    def measure_async_enable(self):
+        """Give the state the second device buffer that measure_start / measure_finish use."""
+        import torch
+        nb = int(self.lib.tn_measure_async_bytes(self.h))
+        self._abuf = torch.empty(nb + 256, dtype=torch.uint8, device=self.arena.device)
+        base = self._abuf.data_ptr()
+        _check(self.lib.tn_measure_async_enable(self.h, ctypes.c_void_p(base + (-base) % 256), nb))
+
+    def measure_start(self, normalize=1):
+        """Snapshot the state and start measuring it; later steps overlap with the measurement."""
+        _check(self.lib.measure_corr_start(self.h, normalize))
+
+    def measure_finish(self, each=False):
+        """Results of the outstanding measure_start, as measure_corr returns them."""
+        L = self.L
+        mean = np.zeros((L, L), dtype=np.complex128)
+        var = np.zeros((L, L))
+        ce = np.zeros((self.B, L, L), dtype=np.complex128) if each else None
+        nrm = np.zeros(self.B)
+        _check(self.lib.measure_corr_finish(self.h, _dp(mean.view(np.float64)), _dp(var),
+                                            _dp(ce.view(np.float64)) if each else None, _dp(nrm)))
+        return mean, var, ce, nrm
+
     # ---- state I/O
     def get_instance(self, inst):
         dims = np.zeros(self.L + 1, dtype=np.int32)

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
@@ -89,12 +90,22 @@ struct tn_state {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     Prof prof2;  // timing of the work launched on aux
+    // asynchronous measurement: a caller-owned second buffer holds a snapshot of the state
+    // (tensors, weights, dims, log-norms, copied in stream order) and the measurement's own
+    // workspace and outputs; the measurement runs on `mstream` while later steps run on `stream`
+    char* abuf = nullptr;
+    size_t a_snap = 0, a_nrm = 0, a_ceach = 0, a_cmean = 0, a_cvar = 0, a_ws = 0, a_total = 0;
+    hipStream_t mstream = nullptr;
+    hipEvent_t ev_snap = nullptr;
+    bool apending = false;
+    Prof prof3;  // timing of the work launched on mstream
     ~tn_state() {
-        if (aux) {
-            hipStreamSynchronize(aux);
-            hipStreamDestroy(aux);
-        }
-        for (hipEvent_t e : {ev_fork, ev_join})
+        for (hipStream_t q : {aux, mstream})
+            if (q) {
+                hipStreamSynchronize(q);
+                hipStreamDestroy(q);
+            }
+        for (hipEvent_t e : {ev_fork, ev_join, ev_snap})
             if (e) hipEventDestroy(e);
     }
 };
@@ -404,7 +415,8 @@ extern "C" int mps_free(void* h) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     if (!s) return fail(TN_EINVAL, "null handle");
     hipStreamSynchronize(s->stream);
-    for (Prof* p : {&s->prof, &s->prof2})
+    if (s->mstream) hipStreamSynchronize(s->mstream);
+    for (Prof* p : {&s->prof, &s->prof2, &s->prof3})
         for (int k = 0; k < TN_K_COUNT; ++k)
             for (auto& pr : p->ev[k]) {
                 hipEventDestroy(pr.first);
@@ -841,8 +853,7 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
 }
 
 // ------------------------------------------------------------------ measurement
-static MeasWork meas_work(tn_state* s, int b0, int nbm) {
-    char* ws = s->arena + s->lay.off_ws;
+static MeasWork meas_work(tn_state* s, char* ws, double2* ceach, double* nrm, int b0, int nbm) {
     MeasWork mw;
     mw.b0 = b0;
     mw.nbm = nbm;
@@ -851,8 +862,8 @@ static MeasWork meas_work(tn_state* s, int b0, int nbm) {
     mw.X = ws + s->lay.m_X;
     mw.Y = ws + s->lay.m_Y;
     mw.W = ws + s->lay.m_W;
-    mw.C = at<double2>(s, s->lay.off_ceach) + (size_t)b0 * s->L * s->L;
-    mw.nrm = at<double>(s, s->lay.off_nrm) + b0;
+    mw.C = ceach + (size_t)b0 * s->L * s->L;
+    mw.nrm = nrm + b0;
     return mw;
 }
 
@@ -894,18 +905,15 @@ __global__ void k_meas_stats(int B, int LL, const double2* Ceach, const double* 
     var[e] = B > 1 ? v / (B - 1) : 0.0;
 }
 
-extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_var, double* C_each, double* norm_out) {
-    tn_state* s = reinterpret_cast<tn_state*>(h);
-    g_err.clear();
-    if (!s) return fail(TN_EINVAL, "null handle");
-    if (!C_mean) return fail(TN_EINVAL, "C_mean is null");
-    DevState ds = dev_state(s);
-    prof_begin(&s->prof, TN_K_MEASURE, s->stream);
+// the measurement sweep of every instance of ds, with workspace ws, per-instance results ce
+// and nr and batch statistics cmean, cvar, all launched on st
+static int run_measure(tn_state* s, const DevState& ds, char* ws, double2* ce, double* nr, double2* cmean,
+                       double* cvar, int normalize, hipStream_t st) {
     for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
         int nbm = std::min(s->nbm, s->B - b0);
-        MeasWork mw = meas_work(s, b0, nbm);
-        if (s->kind == TN_KIND_MPDO) launch_measure_mpdo(s->prec, ds, mw, s->stream);
-        else launch_measure_mps(s->prec, ds, mw, s->stream);
+        MeasWork mw = meas_work(s, ws, ce, nr, b0, nbm);
+        if (s->kind == TN_KIND_MPDO) launch_measure_mpdo(s->prec, ds, mw, st);
+        else launch_measure_mps(s->prec, ds, mw, st);
         HIPCHK(hipGetLastError());
     }
     // normalize 0 and 2 on an MPS keep <psi|O|psi> per instance (linear QSD); 2 also divides the
@@ -913,22 +921,116 @@ extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_va
     const bool linear = s->kind == TN_KIND_MPS && (normalize == 0 || normalize == 2);
     const int ratio = s->kind == TN_KIND_MPS && normalize == 2;
     int mode = s->kind == TN_KIND_MPDO ? 2 : (linear ? 1 : 0);
+    hipLaunchKernelGGL(k_meas_scale, dim3(s->B), dim3(256), 0, st, ds, ce, nr, mode);
+    const int LL = s->L * s->L;
+    hipLaunchKernelGGL(k_meas_stats, dim3((LL + 255) / 256), dim3(256), 0, st, s->B, LL, ce, nr, ratio, cmean, cvar);
+    HIPCHK(hipGetLastError());
+    return TN_OK;
+}
+
+static int copy_measure_out(tn_state* s, const double2* ce, const double* nr, const double2* cmean, const double* cvar,
+                            double* C_mean, double* C_var, double* C_each, double* norm_out, hipStream_t st) {
+    const int LL = s->L * s->L;
+    HIPCHK(hipMemcpyAsync(C_mean, cmean, (size_t)LL * 16, hipMemcpyDeviceToHost, st));
+    if (C_var) HIPCHK(hipMemcpyAsync(C_var, cvar, (size_t)LL * 8, hipMemcpyDeviceToHost, st));
+    if (C_each) HIPCHK(hipMemcpyAsync(C_each, ce, (size_t)s->B * LL * 16, hipMemcpyDeviceToHost, st));
+    if (norm_out) HIPCHK(hipMemcpyAsync(norm_out, nr, (size_t)s->B * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return TN_OK;
+}
+
+extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_var, double* C_each, double* norm_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!C_mean) return fail(TN_EINVAL, "C_mean is null");
+    DevState ds = dev_state(s);
     double2* ce = at<double2>(s, s->lay.off_ceach);
     double* nr = at<double>(s, s->lay.off_nrm);
-    hipLaunchKernelGGL(k_meas_scale, dim3(s->B), dim3(256), 0, s->stream, ds, ce, nr, mode);
-    const int LL = s->L * s->L;
-    hipLaunchKernelGGL(k_meas_stats, dim3((LL + 255) / 256), dim3(256), 0, s->stream, s->B, LL, ce, nr, ratio,
-                       at<double2>(s, s->lay.off_cmean), at<double>(s, s->lay.off_cvar));
-    HIPCHK(hipGetLastError());
+    double2* cm = at<double2>(s, s->lay.off_cmean);
+    double* cv = at<double>(s, s->lay.off_cvar);
+    prof_begin(&s->prof, TN_K_MEASURE, s->stream);
+    int rc = run_measure(s, ds, s->arena + s->lay.off_ws, ce, nr, cm, cv, normalize, s->stream);
+    if (rc != TN_OK) return rc;
     prof_end(&s->prof, TN_K_MEASURE, s->stream);
-    HIPCHK(hipMemcpyAsync(C_mean, s->arena + s->lay.off_cmean, (size_t)LL * 16, hipMemcpyDeviceToHost, s->stream));
-    if (C_var)
-        HIPCHK(hipMemcpyAsync(C_var, s->arena + s->lay.off_cvar, (size_t)LL * 8, hipMemcpyDeviceToHost, s->stream));
-    if (C_each)
-        HIPCHK(hipMemcpyAsync(C_each, ce, (size_t)s->B * LL * 16, hipMemcpyDeviceToHost, s->stream));
-    if (norm_out) HIPCHK(hipMemcpyAsync(norm_out, nr, (size_t)s->B * 8, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
+    return copy_measure_out(s, ce, nr, cm, cv, C_mean, C_var, C_each, norm_out, s->stream);
+}
+
+// ------------------------------------------------------------------ asynchronous measurement
+// offsets inside the second buffer: the snapshot repeats the arena's [off_tens, off_trunc)
+// range byte for byte, so its pointers keep the arena's relative offsets
+static void async_layout(tn_state* s) {
+    size_t o = 0;
+    s->a_snap = o; o = al(o + (s->lay.off_trunc - s->lay.off_tens));
+    s->a_nrm = o; o = al(o + (size_t)s->B * 8);
+    s->a_ceach = o; o = al(o + (size_t)s->B * s->L * s->L * 16);
+    s->a_cmean = o; o = al(o + (size_t)s->L * s->L * 16);
+    s->a_cvar = o; o = al(o + (size_t)s->L * s->L * 8);
+    s->a_ws = o; o = al(o + s->lay.m_bytes);
+    s->a_total = o;
+}
+
+extern "C" size_t tn_measure_async_bytes(const void* h) {
+    const tn_state* c = reinterpret_cast<const tn_state*>(h);
+    if (!c) return 0;
+    tn_state* s = const_cast<tn_state*>(c);
+    async_layout(s);
+    return s->a_total;
+}
+
+extern "C" int tn_measure_async_enable(void* h, void* buf, size_t bytes) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!buf) return fail(TN_EINVAL, "buffer is null");
+    if (reinterpret_cast<uintptr_t>(buf) % 256 != 0) return fail(TN_EINVAL, "buffer is not 256-byte aligned");
+    if (s->apending) return fail(TN_EINVAL, "a measurement is outstanding");
+    async_layout(s);
+    if (bytes < s->a_total) return fail(TN_ENOMEM, "buffer smaller than tn_measure_async_bytes");
+    if (!s->mstream) HIPCHK(hipStreamCreateWithFlags(&s->mstream, hipStreamNonBlocking));
+    if (!s->ev_snap) HIPCHK(hipEventCreateWithFlags(&s->ev_snap, hipEventDisableTiming));
+    s->abuf = reinterpret_cast<char*>(buf);
     return TN_OK;
+}
+
+extern "C" int measure_corr_start(void* h, int normalize) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!s->abuf) return fail(TN_EINVAL, "asynchronous measurement not enabled (tn_measure_async_enable)");
+    if (s->apending) return fail(TN_EINVAL, "a measurement is outstanding (measure_corr_finish)");
+    // snapshot in the order of the work already queued on the state's stream
+    char* snap = s->abuf + s->a_snap;
+    HIPCHK(hipMemcpyAsync(snap, s->arena + s->lay.off_tens, s->lay.off_trunc - s->lay.off_tens,
+                          hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipEventRecord(s->ev_snap, s->stream));
+    HIPCHK(hipStreamWaitEvent(s->mstream, s->ev_snap, 0));
+    DevState ds = dev_state(s);
+    ds.tens = snap;
+    ds.lam = reinterpret_cast<double*>(snap + (s->lay.off_lam - s->lay.off_tens));
+    ds.dims = reinterpret_cast<int*>(snap + (s->lay.off_dims - s->lay.off_tens));
+    ds.lognorm = reinterpret_cast<double*>(snap + (s->lay.off_lognorm - s->lay.off_tens));
+    ds.trunc = nullptr;
+    prof_begin(&s->prof3, TN_K_MEASURE, s->mstream);
+    int rc = run_measure(s, ds, s->abuf + s->a_ws, reinterpret_cast<double2*>(s->abuf + s->a_ceach),
+                         reinterpret_cast<double*>(s->abuf + s->a_nrm), reinterpret_cast<double2*>(s->abuf + s->a_cmean),
+                         reinterpret_cast<double*>(s->abuf + s->a_cvar), normalize, s->mstream);
+    if (rc != TN_OK) return rc;
+    prof_end(&s->prof3, TN_K_MEASURE, s->mstream);
+    s->apending = true;
+    return TN_OK;
+}
+
+extern "C" int measure_corr_finish(void* h, double* C_mean, double* C_var, double* C_each, double* norm_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!s->apending) return fail(TN_EINVAL, "no measurement outstanding (measure_corr_start)");
+    if (!C_mean) return fail(TN_EINVAL, "C_mean is null");
+    s->apending = false;
+    return copy_measure_out(s, reinterpret_cast<double2*>(s->abuf + s->a_ceach),
+                            reinterpret_cast<double*>(s->abuf + s->a_nrm), reinterpret_cast<double2*>(s->abuf + s->a_cmean),
+                            reinterpret_cast<double*>(s->abuf + s->a_cvar), C_mean, C_var, C_each, norm_out, s->mstream);
 }
 
 // ------------------------------------------------------------------ dissipative step
@@ -972,7 +1074,7 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, (size_t)s->B * 8, hipMemcpyHostToDevice, s->stream));
         for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
             int nbm = std::min(s->nbm, s->B - b0);
-            MeasWork mw = meas_work(s, b0, nbm);
+            MeasWork mw = meas_work(s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
             launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals,
                                shifted ? jL.data() : nullptr, lvals, s->stream);
             launch_qt_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam, vals, lvals, mw.nrm,
@@ -994,7 +1096,7 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
         } else {
             for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
                 int nbm = std::min(s->nbm, s->B - b0);
-                MeasWork mw = meas_work(s, b0, nbm);
+                MeasWork mw = meas_work(s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
                 launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals, jL.data(),
                                    lvals, s->stream);
                 launch_qsd_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam,
@@ -1070,7 +1172,8 @@ extern "C" int tn_prof_enable(void* h, int on) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     if (!s) return fail(TN_EINVAL, "null handle");
     hipStreamSynchronize(s->stream);
-    for (Prof* p : {&s->prof, &s->prof2}) {
+    if (s->mstream) hipStreamSynchronize(s->mstream);
+    for (Prof* p : {&s->prof, &s->prof2, &s->prof3}) {
         for (int k = 0; k < TN_K_COUNT; ++k) {
             for (auto& pr : p->ev[k]) {
                 hipEventDestroy(pr.first);
@@ -1100,10 +1203,11 @@ extern "C" int tn_prof_busy(void* h, int kernel_id, double* busy_ms) {
     if (kernel_id < 0 || kernel_id >= TN_K_COUNT) return fail(TN_EINVAL, "bad kernel id");
     if (!busy_ms) return fail(TN_EINVAL, "busy_ms is null");
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->mstream) HIPCHK(hipStreamSynchronize(s->mstream));
     *busy_ms = 0.0;
     if (!s->prof.ref) return TN_OK;
     std::vector<std::pair<double, double>> iv;
-    for (Prof* p : {&s->prof, &s->prof2})
+    for (Prof* p : {&s->prof, &s->prof2, &s->prof3})
         for (auto& pr : p->ev[kernel_id]) {
             float a = 0.0f, b = 0.0f;
             HIPCHK(hipEventElapsedTime(&a, s->prof.ref, pr.first));
@@ -1131,9 +1235,10 @@ extern "C" int tn_prof_query(void* h, int kernel_id, double* total_ms, long long
     if (!s) return fail(TN_EINVAL, "null handle");
     if (kernel_id < 0 || kernel_id >= TN_K_COUNT) return fail(TN_EINVAL, "bad kernel id");
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->mstream) HIPCHK(hipStreamSynchronize(s->mstream));
     double tot = 0.0;
     long long cnt = 0;
-    for (Prof* p : {&s->prof, &s->prof2}) {
+    for (Prof* p : {&s->prof, &s->prof2, &s->prof3}) {
         for (auto& pr : p->ev[kernel_id]) {
             float ms = 0.0f;
             HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
