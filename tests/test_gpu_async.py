@@ -81,3 +81,17 @@ def test_async_measurement_refuses_misuse():
     assert lib.tn_measure_async_enable(st.h, st._abuf.data_ptr() + (-st._abuf.data_ptr()) % 256, nb - 256) \
         == -2  # TN_ENOMEM
     st.close()
+
+
+def test_async_measurement_over_several_instance_groups():
+    # more instances than one measurement group holds (1024), so the sweep runs group by group
+    st, noise = _qsd_state(api.FP64, B=1030, L=4, chi=4, seed=9)
+    _evolve(st, noise, 0, 5)
+    ref = st.measure_corr(normalize=2, each=True)
+    st.measure_async_enable()
+    st.measure_start(2)
+    _evolve(st, noise, 5, 2)
+    got = st.measure_finish(each=True)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    st.close()
