@@ -959,23 +959,25 @@ extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_va
 // ------------------------------------------------------------------ asynchronous measurement
 // offsets inside the second buffer: the snapshot repeats the arena's [off_tens, off_trunc)
 // range byte for byte, so its pointers keep the arena's relative offsets
-static void async_layout(tn_state* s) {
+struct AsyncLayout {
+    size_t snap, nrm, ceach, cmean, cvar, ws, total;
+};
+static AsyncLayout async_layout(const tn_state* s) {
+    AsyncLayout a;
     size_t o = 0;
-    s->a_snap = o; o = al(o + (s->lay.off_trunc - s->lay.off_tens));
-    s->a_nrm = o; o = al(o + (size_t)s->B * 8);
-    s->a_ceach = o; o = al(o + (size_t)s->B * s->L * s->L * 16);
-    s->a_cmean = o; o = al(o + (size_t)s->L * s->L * 16);
-    s->a_cvar = o; o = al(o + (size_t)s->L * s->L * 8);
-    s->a_ws = o; o = al(o + s->lay.m_bytes);
-    s->a_total = o;
+    a.snap = o; o = al(o + (s->lay.off_trunc - s->lay.off_tens));
+    a.nrm = o; o = al(o + (size_t)s->B * 8);
+    a.ceach = o; o = al(o + (size_t)s->B * s->L * s->L * 16);
+    a.cmean = o; o = al(o + (size_t)s->L * s->L * 16);
+    a.cvar = o; o = al(o + (size_t)s->L * s->L * 8);
+    a.ws = o; o = al(o + s->lay.m_bytes);
+    a.total = o;
+    return a;
 }
 
 extern "C" size_t tn_measure_async_bytes(const void* h) {
-    const tn_state* c = reinterpret_cast<const tn_state*>(h);
-    if (!c) return 0;
-    tn_state* s = const_cast<tn_state*>(c);
-    async_layout(s);
-    return s->a_total;
+    const tn_state* s = reinterpret_cast<const tn_state*>(h);
+    return s ? async_layout(s).total : 0;
 }
 
 extern "C" int tn_measure_async_enable(void* h, void* buf, size_t bytes) {
@@ -985,11 +987,18 @@ extern "C" int tn_measure_async_enable(void* h, void* buf, size_t bytes) {
     if (!buf) return fail(TN_EINVAL, "buffer is null");
     if (reinterpret_cast<uintptr_t>(buf) % 256 != 0) return fail(TN_EINVAL, "buffer is not 256-byte aligned");
     if (s->apending) return fail(TN_EINVAL, "a measurement is outstanding");
-    async_layout(s);
-    if (bytes < s->a_total) return fail(TN_ENOMEM, "buffer smaller than tn_measure_async_bytes");
+    const AsyncLayout a = async_layout(s);
+    if (bytes < a.total) return fail(TN_ENOMEM, "buffer smaller than tn_measure_async_bytes");
     if (!s->mstream) HIPCHK(hipStreamCreateWithFlags(&s->mstream, hipStreamNonBlocking));
     if (!s->ev_snap) HIPCHK(hipEventCreateWithFlags(&s->ev_snap, hipEventDisableTiming));
     s->abuf = reinterpret_cast<char*>(buf);
+    s->a_snap = a.snap;
+    s->a_nrm = a.nrm;
+    s->a_ceach = a.ceach;
+    s->a_cmean = a.cmean;
+    s->a_cvar = a.cvar;
+    s->a_ws = a.ws;
+    s->a_total = a.total;
     return TN_OK;
 }
 
