@@ -95,3 +95,22 @@ def test_async_measurement_over_several_instance_groups():
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
     st.close()
+
+
+def test_async_measurement_purified():
+    # a Kraus index on the jump sites: the snapshot holds the wider site tensors as they are
+    L, chi, chik = 6, 16, 4
+    st = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 3, chi, tn_inputs.neel(L), chi_k_max=chik)
+    for _ in range(4):
+        st.tebd_step(0.05, order=1)
+        st.apply_jumps(api.MODE_KRAUS, 0.05)
+    ref = st.measure_corr(each=True)
+    st.measure_async_enable()
+    st.measure_start()
+    for _ in range(2):
+        st.tebd_step(0.05, order=1)
+        st.apply_jumps(api.MODE_KRAUS, 0.05)
+    got = st.measure_finish(each=True)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    st.close()
