@@ -137,8 +137,12 @@ int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
  * Sec. 4.2, histories not renormalized); 2 -> as 0 per instance (C_each, C_var), but C_mean is
  * the ratio sum_b <psi_b|O|psi_b> / sum_b <psi_b|psi_b>; any other nonzero value acts as 1.
  * MPDO: Tr(rho O)/Tr rho; PURIFIED: Tr(X X^+ O)/Tr(X X^+) (normalize ignored).
- * C_mean: L*L complex, batch mean (row i = c_i^+).  C_var: L*L doubles or NULL, batch
- * variance E|C - mean|^2.  C_each: B*L*L complex or NULL.  norm_out: B doubles or
+ * C_mean: L*L complex, batch mean (row i = c_i^+).  C_var: L*L doubles or NULL, the sample
+ * variance of the per-instance values C_b (those C_each holds) with divisor B - 1, around their
+ * arithmetic batch mean: sum_b |C_b - mean|^2 / (B - 1), 0 when B = 1; with normalize 2 it is
+ * still taken around the arithmetic mean of the linear values, not around the ratio C_mean.
+ * sqrt(C_var / B) is the statistical error of eq. ErrorCLT (Sec. 4.1).
+ * C_each: B*L*L complex or NULL.  norm_out: B doubles or
  * NULL: <psi|psi> (MPS, PURIFIED) or Tr rho (MPDO), including exp(lognorm). */
 int measure_corr(void* s, int normalize, double* C_mean, double* C_var, double* C_each,
                  double* norm_out);

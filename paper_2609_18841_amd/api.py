@@ -175,9 +175,12 @@ class State:
         """Give the state the second device buffer that measure_start / measure_finish use."""
         import torch
         nb = int(self.lib.tn_measure_async_bytes(self.h))
-        self._abuf = torch.empty(nb + 256, dtype=torch.uint8, device=self.arena.device)
-        base = self._abuf.data_ptr()
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=self.arena.device)
+        base = buf.data_ptr()
         _check(self.lib.tn_measure_async_enable(self.h, ctypes.c_void_p(base + (-base) % 256), nb))
+        # the library now holds the new buffer; only then may the one it held before be released
+        # (a refused call leaves the old buffer in use by an outstanding measurement)
+        self._abuf = buf
 
     def measure_start(self, normalize=1):
         """Snapshot the state and start measuring it; later steps overlap with the measurement."""

@@ -99,8 +99,15 @@ __global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int ti
     const int dl = d.dl, dr = d.dr, D = dl * dr, cw = 64 / dr, chir = d.chir, n = d.n;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.m || tn * cw >= chir) return;
+    // the gate is staged as G - 1 and the identity part added exactly: a Trotter gate is
+    // 1 + O(dt), and rounding G itself to the working precision would perturb the generator by
+    // ~eps/dt coherently at every step, while rounding G - 1 perturbs it by ~eps |h|
     const double2* g = w.gates + (size_t)d.bond * w.gstride;
-    for (int e = threadIdx.x; e < D * D; e += NT) G[e] = cconv<T>(g[e]);
+    for (int e = threadIdx.x; e < D * D; e += NT) {
+        double2 ge = g[e];
+        if (e / D == e % D) ge.x -= 1.0;
+        G[e] = cconv<T>(ge);
+    }
     const T* P = site_ptr<T>(s, d.b, d.bond);
     const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
     T* out = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
@@ -126,7 +133,7 @@ __global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int ti
 #pragma unroll
         for (int o = 0; o < DM; ++o) {
             if (o < D) {
-                T acc = czero<T>();
+                T acc = v[o];
 #pragma unroll
                 for (int x = 0; x < DM; ++x)
                     if (x < D) cfma(acc, G[o * D + x], v[x]);
@@ -1922,9 +1929,13 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
 }
 
 // ------------------------------------------------------------------ Hastings split
+// B_bond = Theta~ V / s on the FP64 matrix cores in both precisions: V is the FP64 eigenvector
+// matrix and Theta~ enters as stored (complex64 in split mode, converted exactly), so the only
+// rounding of the split is the final store.  FP32 products here would round V and accumulate
+// 2 n terms in FP32 at every update, a per-update error several times that of the store.
 template <class T>
 __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n, double* glog, double* gwt) {
-    __shared__ T As[8 * 64], Bs[8 * 64];
+    __shared__ double2 As[8 * 64], Bs[8 * 64];
     ItemDims d;
     const int j = blockIdx.y;
     if (!item_dims(s, w, j, d)) return;
@@ -1943,7 +1954,7 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     const double2* V = w.V + (size_t)j * w.nmax * w.vld;
     T* Bl = site_ptr<T>(s, d.b, d.bond);
     const int n = d.n, chi = w.vld;
-    const R inv = (R)(1.0 / sv);
+    const double inv = 1.0 / sv;
     if (w.rmove) {
         // centre moves right: B_bond = Theta~ V diag(1/S) (left isometry), B_{bond+1} <- diag(Lambda) V^+
         const double* lam = lam_ptr(s, d.b, d.bond);
@@ -1951,21 +1962,21 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
             T* Br = site_ptr<T>(s, d.b, d.bond + 1);
             for (int e = threadIdx.x; e < k * n; e += NT) Br[e] = cscale(Br[e], (R)lam[e / n]);
         }
-        block_gemm<T, true, true, 8>(
+        block_gemm<double2, true, true, 8>(
             d.m, k, n, tm * 64, tn * 64,
-            [&](int r, int q) { return th[(size_t)r * n + q]; },
-            [&](int q, int c) { return cconv<T>(V[(size_t)q * chi + c]); },
-            [&](int r, int c, T v) {
+            [&](int r, int q) { return cconv<double2>(th[(size_t)r * n + q]); },
+            [&](int q, int c) { return V[(size_t)q * chi + c]; },
+            [&](int r, int c, double2 v) {
                 const double sc = lam[c] > 0.0 ? 1.0 / (lam[c] * sv) : 0.0;
-                Bl[(size_t)r * k + c] = cscale(v, (R)sc);
+                Bl[(size_t)r * k + c] = cconv<T>(cscale(v, sc));
             }, As, Bs);
         return;
     }
-    block_gemm<T, true, true, 8>(
+    block_gemm<double2, true, true, 8>(
         d.m, k, n, tm * 64, tn * 64,
-        [&](int r, int q) { return th[(size_t)r * n + q]; },
-        [&](int q, int c) { return cconv<T>(V[(size_t)q * chi + c]); },
-        [&](int r, int c, T v) { Bl[(size_t)r * k + c] = cscale(v, inv); }, As, Bs);
+        [&](int r, int q) { return cconv<double2>(th[(size_t)r * n + q]); },
+        [&](int q, int c) { return V[(size_t)q * chi + c]; },
+        [&](int r, int c, double2 v) { Bl[(size_t)r * k + c] = cconv<T>(cscale(v, inv)); }, As, Bs);
 }
 
 // ------------------------------------------------------------------ FP64 mode: one-sided Jacobi refinement

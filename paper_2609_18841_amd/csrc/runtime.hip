@@ -883,8 +883,9 @@ __global__ void k_meas_scale(DevState s, double2* Ceach, double* nrm, int mode) 
         else nrm[b] = n * exp(2.0 * s.lognorm[b]);
     }
 }
-// batch mean and variance per entry (fixed summation order); with ratio the mean entry is
-// sum_b C_b / sum_b <psi_b|psi_b> (the variance stays that of the per-instance values)
+// batch mean and sample variance per entry (divisor B - 1, around the arithmetic mean; fixed
+// summation order); with ratio the mean entry is sum_b C_b / sum_b <psi_b|psi_b> (the variance
+// stays that of the per-instance values around their arithmetic mean)
 __global__ void k_meas_stats(int B, int LL, const double2* Ceach, const double* nrm, int ratio, double2* mean,
                              double* var) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;

@@ -71,10 +71,18 @@ def test_async_measurement_refuses_misuse():
     st.measure_async_enable()
     with pytest.raises(api.TnError):
         st.measure_finish()  # nothing outstanding
+    snap = st.measure_corr(normalize=0, each=True)
     st.measure_start(0)
     with pytest.raises(api.TnError):
         st.measure_start(0)  # one outstanding at a time
-    st.measure_finish()
+    held = st._abuf
+    with pytest.raises(api.TnError):
+        st.measure_async_enable()  # refused while a measurement is outstanding ...
+    assert st._abuf is held  # ... and the buffer that measurement writes stays alive
+    _evolve(st, noise, 0, 2)
+    got = st.measure_finish(each=True)
+    for a, b in zip(got, snap):
+        assert np.array_equal(a, b)
     lib = st.lib
     assert lib.tn_measure_async_enable(st.h, None, 1 << 20) == -1  # TN_EINVAL
     nb = int(lib.tn_measure_async_bytes(st.h))

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import tn_inputs
-from oracle import model as M, tebd, measure, stochastic, kraus, exact
+from oracle import model as M, tebd, measure, stochastic, kraus, exact, stats
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +130,60 @@ def test_qsd_batch_estimators_match_oracle(prec, tol):
     # per instance, mode 2 returns the linear values of mode 0
     assert np.array_equal(each0, each2) and np.array_equal(n0, n2) and np.array_equal(var0, var2)
     assert _normwise(C_rat, C_lin) > 0.1  # the two estimators differ by 17 % at this sample
+
+
+@pytest.mark.parametrize("normalize", [0, 1, 2])
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_batch_variance_matches_oracle_mps(normalize, prec, tol):
+    """eq. ErrorCLT: C_var is the sample variance (divisor B - 1) of the per-history values
+    around their arithmetic mean, E|C_b - mean|^2 per entry; the per-history values are
+    <psi|O|psi> (normalize 0 and 2) or <psi|O|psi>/<psi|psi> (normalize 1)."""
+    L, chi, dt, nsteps, B = 6, 8, 0.05, 12, 5
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    noise = tn_inputs.normals(4321, (nsteps, B, 2, 2))
+    fn = _oracle_gate_fn(mdl, "mps")
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ, precision=prec,
+                  sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    for k in range(nsteps):
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_QSD, dt, noise[k].reshape(-1), api.NOISE_GAUSS)
+    _, var, _, _ = g.measure_corr(normalize=normalize)
+    g.close()
+    vals = []
+    for b in range(B):
+        st = tebd.product_state(occ, "mps")
+        for k in range(nsteps):
+            stochastic.qsd_step(st, mdl.jumps, dt, noise[k, b].reshape(-1), fn, chi, 1e-12)
+        vals.append(measure.corr_mps(st, normalize=(normalize == 1))[0])
+    var_o = stats.batch_variance(np.stack(vals))
+    assert np.max(var_o) > 1e-4  # the histories differ
+    assert _normwise(var, var_o) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_batch_variance_matches_oracle_mpdo(prec, tol):
+    """The same statistic over a batch of density matrices started from different occupations
+    (Tr(rho O)/Tr rho per instance)."""
+    L, chi, dt, nsteps = 6, 64, 0.05, 6
+    occs = [tn_inputs.neel(L), [0] * L, [1, 1, 0, 0, 1, 0], [0, 1, 1, 0, 0, 1]]
+    mdl = M.Model(L)
+    fn = _oracle_gate_fn(mdl, "mpdo")
+    g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), len(occs), chi, occs[0], precision=prec,
+                  sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    vals = []
+    for b, occ in enumerate(occs):
+        st = tebd.product_state(occ, "mpdo")
+        g.set_instance(b, st.tensors, st.lams, 0.0)
+        for _ in range(nsteps):
+            tebd.trotter_step(st, fn, 2, dt, chi, 1e-12)
+        vals.append(measure.corr_mpdo(st)[0])
+    g.tebd_step(dt, order=2, n_steps=nsteps)
+    _, var, _, _ = g.measure_corr()
+    g.close()
+    var_o = stats.batch_variance(np.stack(vals))
+    assert np.max(var_o) > 1e-3
+    assert _normwise(var, var_o) < tol
 
 
 def test_qt_batch_matches_oracle_jump_by_jump():

@@ -686,3 +686,75 @@ def test_sweep_schedule_follows_the_paper_for_first_order():
     expect = [(0, 0, R), (1, -1, R), (2, 0, R), (3, -1, R), (4, 0, R),
               (4, -1, Lf), (3, 1, Lf), (2, -1, Lf), (1, 1, Lf), (0, -1, Lf)]
     assert sweep.sweep_schedule(6, 1) == expect
+
+
+# ---- eq. ErrorCLT: batch statistics (oracle/stats.py) and the current of Sec. 2.1
+
+def test_density_current_obeys_the_continuity_equation():
+    """Sec. 2.1: d<n_i>/dt = <j_i> - <j_{i+1}> in the bulk, with the source and sink adding
+    gamma (1 - n_1) and -gamma n_N at the ends; d<n_i>/dt by central differences of the closed
+    form, so a wrong sign or index in the current fails."""
+    from oracle import exact
+    occ, t, h, g = [1, 0, 1, 0, 1, 0], 0.8, 1e-4, 0.5
+    n_m, _ = exact.density_current(exact.c_exact(t - h, occ, gamma=g))
+    n_p, _ = exact.density_current(exact.c_exact(t + h, occ, gamma=g))
+    n, j = exact.density_current(exact.c_exact(t, occ, gamma=g))
+    dn = (n_p - n_m) / (2 * h)
+    assert np.max(np.abs(dn[1:-1] - (j[:-1] - j[1:]))) < 1e-6
+    assert abs(dn[0] - (g * (1 - n[0]) - j[0])) < 1e-6
+    assert abs(dn[-1] - (j[-1] - g * n[-1])) < 1e-6
+    assert np.max(np.abs(j)) > 0.05  # a current flows at this time
+
+
+def test_batch_variance_special_cases():
+    """Identical histories: variance and CLT error 0.  Two histories: the sample variance with
+    divisor B - 1 is |X_1 - X_2|^2 / 2, entry by entry, for complex entries."""
+    from oracle import stats
+    g = np.random.default_rng(11)
+    X = g.standard_normal((3, 4)) + 1j * g.standard_normal((3, 4))
+    same = np.stack([X] * 5)
+    assert np.max(np.abs(stats.batch_mean(same) - X)) < 1e-15 * np.max(np.abs(X))
+    assert np.max(stats.batch_variance(same)) < 1e-30
+    assert np.max(stats.clt_error(same)) < 1e-15
+    Y = g.standard_normal((3, 4)) + 1j * g.standard_normal((3, 4))
+    two = np.stack([X, Y])
+    assert np.max(np.abs(stats.batch_variance(two) - np.abs(X - Y) ** 2 / 2)) < 1e-14
+    assert np.max(np.abs(stats.clt_error(two) - np.abs(X - Y) / 2)) < 1e-14
+    assert np.array_equal(stats.batch_variance(X[None]), np.zeros((3, 4)))
+
+
+def test_batch_variance_of_a_known_distribution():
+    """Complex Gaussian draws with E|z - mu|^2 = s2: the sample variance is s2 within five of its
+    standard deviations (|z - mu|^2 is exponential, so that deviation is s2 / sqrt(B))."""
+    from oracle import stats
+    g = np.random.default_rng(12)
+    B, s2, mu = 4000, 2.5, 0.3 - 0.7j
+    z = mu + np.sqrt(s2 / 2) * (g.standard_normal((B, 3)) + 1j * g.standard_normal((B, 3)))
+    v = stats.batch_variance(z)
+    assert np.all(np.abs(v - s2) < 5 * s2 / np.sqrt(B))
+    assert np.all(np.abs(stats.batch_mean(z) - mu) < 5 * np.sqrt(s2 / B))
+
+
+def test_clt_error_covers_the_mean_at_its_confidence():
+    """eq. ErrorCLT: over many batches of 50 normal draws, |mean - mu| < 2 sqrt(var/B) holds for
+    about 95 % of them (Student t with 49 degrees of freedom: 94.9 %)."""
+    from oracle import stats
+    g = np.random.default_rng(13)
+    hits = 0
+    trials = 2000
+    for _ in range(trials):
+        x = 1.7 + 0.4 * g.standard_normal(50)
+        hits += abs(stats.batch_mean(x) - 1.7) < 2 * stats.clt_error(x)
+    assert 0.93 < hits / trials < 0.965
+
+
+def test_ratio_mean_divides_out_the_norms():
+    """Sec. 4.2 ratio estimator: when every history's normalized expectation is the same c,
+    sum_b <psi_b|O|psi_b> / sum_b <psi_b|psi_b> is c exactly, while the plain mean is not."""
+    from oracle import stats
+    g = np.random.default_rng(14)
+    norms = 0.5 + g.random(7)
+    c = np.array([[0.25, 0.1 - 0.2j], [0.1 + 0.2j, 0.6]])
+    X = norms[:, None, None] * c[None]
+    assert np.max(np.abs(stats.ratio_mean(X, norms) - c)) < 1e-15
+    assert np.max(np.abs(stats.batch_mean(X) - c)) > 1e-3
