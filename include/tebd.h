@@ -171,6 +171,24 @@ int tn_measure_async_enable(void* s, void* buf, size_t bytes);
 int measure_corr_start(void* s, int normalize);
 int measure_corr_finish(void* s, double* C_mean, double* C_var, double* C_each, double* norm_out);
 
+/* ---- measurement without device allocation --------------------------------- */
+
+/* For callers that cannot allocate device memory or hand the library a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * The same measurement as measure_corr, same arguments, outputs and errors, bit for bit the same
+ * results, but the sweep's workspace (right environments, left strings, GEMM temporaries) is a
+ * static device array of TN_SCRATCH_BYTES inside the library instead of the arena's workspace
+ * region; the instances are measured in groups of as many as that array holds.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and creates nothing.
+ * Every state on one GPU shares that GPU's one array, which keeps the last call's contents
+ * (the sweep writes every entry it reads, so nothing needs clearing): calls that overlap on one
+ * GPU, from two threads or on two streams, race and must not be made.
+ * TN_ENOMEM when one instance's workspace exceeds TN_SCRATCH_BYTES (e.g. MPS, FP64, L = 64,
+ * chi = 256: 272 MB); TN_EHIP if the array's device address could not be looked up at mps_alloc. */
+#define TN_SCRATCH_BYTES ((size_t)128 << 20)
+int measure_corr_noalloc(void* s, int normalize, double* C_mean, double* C_var, double* C_each,
+                         double* norm_out);
+
 /* Release the handle (not the arena). */
 int mps_free(void* s);
 

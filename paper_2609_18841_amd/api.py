@@ -171,6 +171,18 @@ class State:
                                      _dp(ce.view(np.float64)) if each else None, _dp(nrm)))
         return mean, var, ce, nrm
 
+    def measure_corr_noalloc(self, normalize=1, each=False):
+        """measure_corr with the sweep's workspace in the library's static scratch (allocates no
+        device memory); same results."""
+        L = self.L
+        mean = np.zeros((L, L), dtype=np.complex128)
+        var = np.zeros((L, L))
+        ce = np.zeros((self.B, L, L), dtype=np.complex128) if each else None
+        nrm = np.zeros(self.B)
+        _check(self.lib.measure_corr_noalloc(self.h, normalize, _dp(mean.view(np.float64)), _dp(var),
+                                             _dp(ce.view(np.float64)) if each else None, _dp(nrm)))
+        return mean, var, ce, nrm
+
     def measure_async_enable(self):
         """Give the state the second device buffer that measure_start / measure_finish use."""
         import torch

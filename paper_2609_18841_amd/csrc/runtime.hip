@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -99,6 +100,8 @@ struct tn_state {
     hipEvent_t ev_snap = nullptr;
     bool apending = false;
     Prof prof3;  // timing of the work launched on mstream
+    // this device's address of the static measurement scratch (measure_corr_noalloc)
+    char* scratch = nullptr;
     ~tn_state() {
         for (hipStream_t q : {aux, mstream})
             if (q) {
@@ -133,6 +136,20 @@ static int physical_dims(int kind, int L, int chik, const std::vector<int>& jsit
     if (kind == TN_KIND_PURIFIED)
         for (int s : jsite) d[s] = 2 * chik;
     return 0;
+}
+
+// measurement workspace of a group of nbm instances (right environments, left strings and the
+// GEMM temporaries of the sweep); sets ly.m_* and returns ly.m_bytes
+static size_t meas_sublayout(Layout& ly, int L, int chi, int dmax, size_t esz, int nbm) {
+    size_t m = 0;
+    size_t cc = (size_t)chi * chi;
+    ly.m_R = m; m = al(m + std::max((size_t)(L + 1) * nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
+    ly.m_E = m; m = al(m + std::max((size_t)nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
+    ly.m_X = m; m = al(m + (size_t)nbm * L * cc * esz);
+    ly.m_Y = m; m = al(m + (size_t)nbm * L * chi * dmax * chi * esz);
+    ly.m_W = m; m = al(m + (size_t)nbm * chi * dmax * chi * esz);
+    ly.m_bytes = m;
+    return m;
 }
 
 static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax, int prec, int chunk, int nbm,
@@ -192,15 +209,7 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.u_lsel = u; u = al(u + (size_t)chunk * nmax * 8);
     ly.u_fb = u; u = al(u + (size_t)chunk * 4);
     ly.u_bytes = u;
-    // measurement workspace
-    size_t m = 0;
-    size_t cc = (size_t)chi * chi;
-    ly.m_R = m; m = al(m + std::max((size_t)(L + 1) * nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
-    ly.m_E = m; m = al(m + std::max((size_t)nbm * cc * esz, (size_t)nbm * (L + 1) * chi * 16));
-    ly.m_X = m; m = al(m + (size_t)nbm * L * cc * esz);
-    ly.m_Y = m; m = al(m + (size_t)nbm * L * chi * dmax * chi * esz);
-    ly.m_W = m; m = al(m + (size_t)nbm * chi * dmax * chi * esz);
-    ly.m_bytes = m;
+    meas_sublayout(ly, L, chi, dmax, esz, nbm);
     ly.ws_bytes = std::max((size_t)nslots * ly.u_bytes, ly.m_bytes);
     ly.total = ly.off_ws + ly.ws_bytes;
     (void)kind;
@@ -279,6 +288,36 @@ extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double
                                 double lognorm);
 extern "C" int mps_replicate(void* h, int src);
 
+// ------------------------------------------------------------------ static measurement scratch
+// The workspace of measure_corr_noalloc: a file-scope device array that every GPU the library
+// runs on holds, at its own address, until the process ends.  Host code never passes the array's
+// name to a kernel or a copy (on the host it is only a stand-in for the symbol): the device
+// address is looked up once per device with that device current, kept in g_scratch, and used
+// from then on.
+static __device__ __align__(256) char scratch[TN_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, char*> g_scratch;
+
+static int scratch_setup(int dev, char** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) {
+        *out = it->second;
+        return TN_OK;
+    }
+    int prev = -1;
+    HIPCHK(hipGetDevice(&prev));
+    if (prev != dev) HIPCHK(hipSetDevice(dev));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != dev) HIPCHK(hipSetDevice(prev));
+    if (e != hipSuccess || !ptr)
+        return fail(TN_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = reinterpret_cast<char*>(ptr);
+    *out = reinterpret_cast<char*>(ptr);
+    return TN_OK;
+}
+
 extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch, int chi_max, int chi_k_max,
                          int precision, const int* init_occ, double sv_cutoff, void* arena, size_t arena_bytes,
                          void* hip_stream) {
@@ -347,6 +386,18 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
     }
     s->arena = reinterpret_cast<char*>(arena);
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    {
+        // the arena's device holds this state; its copy of the static scratch is looked up now
+        int dev = -1;
+        hipPointerAttribute_t pa;
+        if (hipPointerGetAttributes(&pa, arena) == hipSuccess && pa.device >= 0) dev = pa.device;
+        else if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+        const int rc0 = dev < 0 ? fail(TN_EHIP, "cannot tell the arena's device") : scratch_setup(dev, &s->scratch);
+        if (rc0 != TN_OK) {
+            delete s;
+            return rc0;
+        }
+    }
     if (s->nslots == 2) {
         bool ok = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
         for (hipEvent_t* e : {&s->ev_fork, &s->ev_join})
@@ -853,15 +904,15 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
 }
 
 // ------------------------------------------------------------------ measurement
-static MeasWork meas_work(tn_state* s, char* ws, double2* ceach, double* nrm, int b0, int nbm) {
+static MeasWork meas_work(const Layout& ly, tn_state* s, char* ws, double2* ceach, double* nrm, int b0, int nbm) {
     MeasWork mw;
     mw.b0 = b0;
     mw.nbm = nbm;
-    mw.R = ws + s->lay.m_R;
-    mw.E = ws + s->lay.m_E;
-    mw.X = ws + s->lay.m_X;
-    mw.Y = ws + s->lay.m_Y;
-    mw.W = ws + s->lay.m_W;
+    mw.R = ws + ly.m_R;
+    mw.E = ws + ly.m_E;
+    mw.X = ws + ly.m_X;
+    mw.Y = ws + ly.m_Y;
+    mw.W = ws + ly.m_W;
     mw.C = ceach + (size_t)b0 * s->L * s->L;
     mw.nrm = nrm + b0;
     return mw;
@@ -909,10 +960,12 @@ __global__ void k_meas_stats(int B, int LL, const double2* Ceach, const double* 
 // the measurement sweep of every instance of ds, with workspace ws, per-instance results ce
 // and nr and batch statistics cmean, cvar, all launched on st
 static int run_measure(tn_state* s, const DevState& ds, char* ws, double2* ce, double* nr, double2* cmean,
-                       double* cvar, int normalize, hipStream_t st) {
-    for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
-        int nbm = std::min(s->nbm, s->B - b0);
-        MeasWork mw = meas_work(s, ws, ce, nr, b0, nbm);
+                       double* cvar, int normalize, hipStream_t st, const Layout* mly = nullptr, int group = 0) {
+    const Layout& ly = mly ? *mly : s->lay;
+    const int gsz = group > 0 ? group : s->nbm;
+    for (int b0 = 0; b0 < s->B; b0 += gsz) {
+        int nbm = std::min(gsz, s->B - b0);
+        MeasWork mw = meas_work(ly, s, ws, ce, nr, b0, nbm);
         if (s->kind == TN_KIND_MPDO) launch_measure_mpdo(s->prec, ds, mw, st);
         else launch_measure_mps(s->prec, ds, mw, st);
         HIPCHK(hipGetLastError());
@@ -954,6 +1007,36 @@ extern "C" int measure_corr(void* h, int normalize, double* C_mean, double* C_va
     int rc = run_measure(s, ds, s->arena + s->lay.off_ws, ce, nr, cm, cv, normalize, s->stream);
     if (rc != TN_OK) return rc;
     prof_end(&s->prof, TN_K_MEASURE, s->stream);
+    return copy_measure_out(s, ce, nr, cm, cv, C_mean, C_var, C_each, norm_out, s->stream);
+}
+
+extern "C" int measure_corr_noalloc(void* h, int normalize, double* C_mean, double* C_var, double* C_each,
+                                    double* norm_out) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (!C_mean) return fail(TN_EINVAL, "C_mean is null");
+    if (!s->scratch) return fail(TN_EHIP, "the static scratch of this state's device was not set up");
+    // the largest group of instances whose workspace fits the scratch (at most the arena path's)
+    Layout ml = s->lay;
+    const size_t one = meas_sublayout(ml, s->L, s->chi, s->dmax, s->esz, 1);
+    if (one > TN_SCRATCH_BYTES) {
+        char buf[192];
+        snprintf(buf, sizeof buf,
+                 "measure_corr_noalloc: one instance needs %zu bytes of measurement workspace, above the "
+                 "static scratch of %zu bytes (TN_SCRATCH_BYTES)", one, (size_t)TN_SCRATCH_BYTES);
+        return fail(TN_ENOMEM, buf);
+    }
+    int group = (int)std::min<size_t>((size_t)std::min(s->nbm, s->B), TN_SCRATCH_BYTES / one);
+    while (group > 1 && meas_sublayout(ml, s->L, s->chi, s->dmax, s->esz, group) > TN_SCRATCH_BYTES) --group;
+    meas_sublayout(ml, s->L, s->chi, s->dmax, s->esz, group);
+    DevState ds = dev_state(s);
+    double2* ce = at<double2>(s, s->lay.off_ceach);
+    double* nr = at<double>(s, s->lay.off_nrm);
+    double2* cm = at<double2>(s, s->lay.off_cmean);
+    double* cv = at<double>(s, s->lay.off_cvar);
+    int rc = run_measure(s, ds, s->scratch, ce, nr, cm, cv, normalize, s->stream, &ml, group);
+    if (rc != TN_OK) return rc;
     return copy_measure_out(s, ce, nr, cm, cv, C_mean, C_var, C_each, norm_out, s->stream);
 }
 
@@ -1084,7 +1167,7 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_rnd, rnd, (size_t)s->B * 8, hipMemcpyHostToDevice, s->stream));
         for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
             int nbm = std::min(s->nbm, s->B - b0);
-            MeasWork mw = meas_work(s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
+            MeasWork mw = meas_work(s->lay, s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
             launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals,
                                shifted ? jL.data() : nullptr, lvals, s->stream);
             launch_qt_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam, vals, lvals, mw.nrm,
@@ -1106,7 +1189,7 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
         } else {
             for (int b0 = 0; b0 < s->B; b0 += s->nbm) {
                 int nbm = std::min(s->nbm, s->B - b0);
-                MeasWork mw = meas_work(s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
+                MeasWork mw = meas_work(s->lay, s, s->arena + s->lay.off_ws, at<double2>(s, s->lay.off_ceach), at<double>(s, s->lay.off_nrm), b0, nbm);
                 launch_jump_expect(s->prec, ds, mw, s->njump, s->model.jump_site.data(), jl.data(), vals, jL.data(),
                                    lvals, s->stream);
                 launch_qsd_apply(s->prec, ds, b0, nbm, dt, s->njump, jsite, jop, gam,
