@@ -3,16 +3,21 @@
 Workload (one bench step = one output interval of a quantum-state-diffusion batch):
   B trajectories of the boundary-driven free-fermion chain (J = 1, gamma = 0.5, source s+ on
   the first site, sink s- on the last), L = 64 sites, bond dimension chi = 64, SPLIT precision
-  (complex64 MFMA contractions, FP64 Gram/eigensolver/weights/norms); per bench step:
-    INNER first-order Trotter steps (dt = 0.01) of exp(-i h^eff dt) gates, each followed by the
-    diffusion factors 1 + dW sqrt(gamma) L with complex Gaussian dW, then one measurement of
-    C_ij = <c_i^+ c_j> for every trajectory (the output time).
-  Inputs are synthetic and seeded: a right-isometric MPS with geometric bond weights
-  (sigma_a ~ exp(-a/8)) at chi = 64 on every saturated bond stands in for a pre-evolved state.
-Reported: value = two-site updates/s of the batched split path (whole job), the plain
-per-instance FP64 GPU path for comparison, the roofline fraction of the dominant kernel
-(HIP events on the library stream), value as a fraction of the path's flop-model bound, and the
-CPU oracle timed on a bounded sample (one core, and one process per core).
+  (complex64 storage, FP32 MFMA Theta with the gate, FP64 Gram/eigensolver/split/weights/norms);
+  per bench step: INNER first-order Trotter steps (dt = 0.01) of exp(-i h^eff dt) gates, each
+  followed by the diffusion factors 1 + dW sqrt(gamma) L with complex Gaussian dW, then one
+  measurement of C_ij = <c_i^+ c_j> for every trajectory (the output time).
+Inputs are synthetic and seeded.  The headline starts from physical checkpoints: a few
+trajectories evolved from the Neel state with the library's FP64 path until the middle bonds
+saturate chi, copied over the batch.  A second figure starts from right-isometric tensors with
+geometric bond weights (sigma_a ~ exp(-a/8)).
+Reported: value = two-site updates/s of the batched split path (whole job, timed with kernel
+timing off so the captured HIP graphs replay), the plain per-instance and the batched FP64 GPU
+paths for comparison, the error against the FP64 oracle after one interval and after 100 steps
+with the tolerance, the roofline of the dominant kernel from a separate pass with kernel timing
+on and the chunks of a layer on one stream (algorithmic flops of the actual bond shapes over
+the HIP-event durations), value against the path's flop-model bound, and the CPU oracle timed
+on a bounded sample (one core, and one process per core).
 """
 import argparse
 import json
@@ -73,6 +78,54 @@ def path_model(d=2, chi=64):
     return {"flops_per_update": f32 + f64, "t_min_us": t * 1e6, "bound_updates_per_s": 1.0 / t}
 
 
+def item_flops(chil, chim, chir, k, d=2):
+    """Algorithmic real flops of one two-site update with bond dimensions (chi_l, chi_m, chi_r), k kept
+    (Theta is (d chi_l) x (d chi_r), Gram order n = d chi_r), per timing bucket: the closed forms of
+    algo_flops at the item's own shape."""
+    m, n = d * chil, d * chir
+    D = d * d
+    return {
+        "theta": 8.0 * m * n * chim + 8.0 * D * D * chil * chir,
+        "gram": 8.0 * m * n * (n + 1) / 2,
+        "hetrd": 16.0 / 3.0 * n ** 3,
+        "vecs": 8.0 * n * n * k,
+        "split": 8.0 * m * n * k,
+    }
+
+
+def item_t_min(chil, chim, chir, k, d=2):
+    """Lower-bound time (s) of one update at its own shape, the model of path_model: Theta, gate and
+    reconstruction at the FP32 matrix peak; the Gram matrix (8 m n^2) and the Hermitian eigensolve
+    (4 (4/3 + 2) n^3) at the FP64 peak."""
+    m, n = d * chil, d * chir
+    f32 = 8.0 * m * n * chim + 8.0 * (d * d) ** 2 * chil * chir + 8.0 * m * n * k
+    f64 = 8.0 * m * n * n + 4.0 * (4.0 / 3.0 + 2.0) * n ** 3
+    return f32 / PEAK["fp32"] + f64 / PEAK["fp64"]
+
+
+def layer_items(dims):
+    """(chi_l, chi_m, chi_r, k) of every two-site update of one first-order Trotter step of one
+    instance whose bond dimensions dims (L + 1 entries) hold from step to step (a saturated
+    state): parity 0 (bonds 0, 2, ...) then parity 1, each bond keeping its dimension, k = chi_m."""
+    L = len(dims) - 1
+    return [(int(dims[b]), int(dims[b + 1]), int(dims[b + 2]), int(dims[b + 1]))
+            for parity in (0, 1) for b in range(parity, L - 1, 2)]
+
+
+def step_work(all_dims):
+    """Per first-order Trotter step of a batch whose instances have bond dimensions all_dims: the
+    algorithmic flops of each timing bucket, the number of updates and the summed t_min (s)."""
+    tot = {"theta": 0.0, "gram": 0.0, "hetrd": 0.0, "vecs": 0.0, "split": 0.0}
+    n_items, tmin = 0, 0.0
+    for dims in all_dims:
+        for chil, chim, chir, k in layer_items(dims):
+            for key, v in item_flops(chil, chim, chir, k).items():
+                tot[key] += v
+            tmin += item_t_min(chil, chim, chir, k)
+            n_items += 1
+    return tot, n_items, tmin
+
+
 def profiled_traffic(kernel):
     """HBM bytes per launch of the timing bucket whose kernel is `kernel` (the sum over its template
     instances: the Householder reduction is a head and a tail dispatch) from the committed counter
@@ -112,12 +165,22 @@ def parse():
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--inner", type=int, default=10, help="Trotter steps per output interval")
     ap.add_argument("--dt", type=float, default=0.01)
-    ap.add_argument("--plain-instances", type=int, default=2)
+    ap.add_argument("--theta-bits", type=int, choices=[32, 64], default=64,
+                    help="matrix cores of the Theta contraction in split mode (the other is timed beside it)")
+    ap.add_argument("--input", choices=["physical", "synthetic"], default="physical",
+                    help="headline input: evolved checkpoints (default) or geometric-spectrum tensors")
+    ap.add_argument("--checkpoints", type=int, default=16, help="distinct evolved trajectories copied over the batch")
+    ap.add_argument("--ck-dt", type=float, default=0.05, help="time step of the checkpoint evolution (FP64)")
+    ap.add_argument("--ck-tmax", type=float, default=20.0, help="longest checkpoint evolution")
+    ap.add_argument("--plain-steps", type=int, default=10, help="Trotter steps per timed run of the plain FP64 path")
+    ap.add_argument("--fp64-batched-steps", type=int, default=2,
+                    help="timed Trotter steps of the batched FP64 path at the full batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock window of the all-core oracle run (the single-core run takes up to 6 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the second input's throughput")
     ap.add_argument("--overlap-measure", action="store_true",
                     help="measure each output from a snapshot, beside the next interval's steps")
     ap.add_argument("--check-steps", type=int, default=100,
@@ -129,17 +192,61 @@ def parse():
 
 # relative singular-value cutoff of the timed state (split precision) and of the FP64 paths
 SV_CUTOFF = {"split": 1e-6, "fp64": 1e-12}
+# the split path's stated bound on correlations against the FP64 oracle, normwise
+# max |dC| / max |C| (the precision pattern's tolerance for FP32 contractions)
+ERR_TOLERANCE = 1e-5
 
 
-def make_state(api, tn_inputs, prec, B, L, chi, seed=2024):
+def evolve_checkpoints(api, tn_inputs, L, chi, n, dt, tmax, seed=4242):
+    """n quantum-state-diffusion trajectories of the workload's chain evolved from the Neel state with
+    the FP64 path (first-order Trotter steps of size dt, each followed by the noise) until chi binds
+    on every bond at least 6 sites from both ends also under the split path's cutoff: the bond
+    holds chi weights and the smallest is above 10 x SV_CUTOFF["split"] of the largest (from the
+    Neel state at dt = 0.05 that is t = 2.5 to 3); or until tmax.  Returns the packed instances
+    [(tensors, lams, lognorm)], the time reached and the bond dimensions."""
+    model = api.Model.free_fermion(L, 1.0, 0.5)
+    st = api.State(api.KIND_MPS, model, n, chi, tn_inputs.neel(L), precision=api.FP64,
+                   sv_cutoff=SV_CUTOFF["fp64"])
+    nmax = int(round(tmax / dt))
+    noise = tn_inputs.normals(seed, (nmax, n * 4))
+    k = 0
+    while k < nmax:
+        st.tebd_step(dt, order=1)
+        st.apply_jumps(api.MODE_QSD, dt, noise[k], api.NOISE_GAUSS)
+        k += 1
+        if k % 5 == 0:
+            lam = [st.lams(b) for b in range(n)]
+            if all(len(l) == chi and l[-1] > 10 * SV_CUTOFF["split"] * l[0] for x in lam for l in x[5:L - 6]):
+                break
+    cks = []
+    for b in range(n):
+        t, lam, ln, _ = st.get_instance(b)
+        cks.append((t, lam, ln))
+    dims = [st.dims(b).tolist() for b in range(n)]
+    st.close()
+    return cks, k * dt, dims
+
+
+def make_state(api, tn_inputs, prec, B, L, chi, cks=None, seed=2024, bits=64):
+    """A batch of B trajectories at bond dimension chi: instance b starts from checkpoint b mod
+    len(cks), or, without checkpoints, every instance from the geometric-spectrum tensors; in split
+    precision Theta is formed on the matrix cores of `bits`.  Returns the state and the FP64 start
+    of instance 0 (tensors, lams, lognorm)."""
     model = api.Model.free_fermion(L, 1.0, 0.5)
     st = api.State(api.KIND_MPS, model, B, chi, tn_inputs.neel(L), precision=prec,
                    sv_cutoff=SV_CUTOFF["split"] if prec == api.SPLIT else SV_CUTOFF["fp64"])
-    tensors, lams, dims = tn_inputs.random_isometric_mps(seed, L, chi)
-    st.set_instance(0, tensors, lams, 0.0)
-    if B > 1:
-        st.replicate(0)
-    return st, (tensors, lams)
+    if prec == api.SPLIT:
+        st.theta_precision(bits)
+    if cks is None:
+        tensors, lams, dims = tn_inputs.random_isometric_mps(seed, L, chi)
+        st.set_instance(0, tensors, lams, 0.0)
+        if B > 1:
+            st.replicate(0)
+        return st, (tensors, lams, 0.0)
+    for b in range(B):
+        t, lam, ln = cks[b % len(cks)]
+        st.set_instance(b, t, lam, ln)
+    return st, cks[0]
 
 
 def run_interval(api, st, noise, inner, dt, measure=True):
@@ -226,14 +333,15 @@ def cpu_baseline(L, chi, dt, budget_s, procs=None):
                       f"single core: {upd1} updates in {b - a:.1f} s"}
 
 
-def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0):
-    """{steps: (err, spread, err_density, err_nn)} for trajectory 0 at each checkpoint of C_gpu0
-    ({steps: C}).  err and spread are max |dC| / max |C|: err is the GPU against the FP64 oracle on
-    the same input and with the same truncation (chi and the split state's singular-value cutoff);
-    spread is the oracle against itself with another LAPACK SVD driver (gesvd instead of gesdd).
-    At a binding chi the kept singular vectors depend on rounding inside the SVD, and spread is the
-    scale at which two exact FP64 runs already differ.  err_density and err_nn are the GPU's
-    elementwise relative errors on the diagonal (densities) and on the first off-diagonal."""
+def _oracle_corr_run(job):
+    """One FP64 oracle trajectory from start (tensors, lams, lognorm) under the given noise rows with
+    the given LAPACK driver; {steps: C} at the requested step counts (BLAS one thread).  Driver
+    "c64start" is gesdd from the start's tensors rounded to complex64: the spread that storing the
+    start in the split path's precision alone causes."""
+    start, L, chi, dt, noise, want, driver = job
+    if driver == "c64start":
+        start = ([t.astype(np.complex64).astype(np.complex128) for t in start[0]],) + tuple(start[1:])
+        driver = "gesdd"
     from threadpoolctl import threadpool_limits
     from oracle import model as M, tebd, stochastic, measure
     mdl = M.Model(L)
@@ -243,22 +351,56 @@ def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0):
         if (b, tau) not in cache:
             cache[(b, tau)] = M.gate_heff(mdl, b, tau)
         return cache[(b, tau)]
-    tensors, lams = st_init
-    last = max(C_gpu0)
-    Cs = {"gesdd": {}, "gesvd": {}}
+    tensors, lams = start[0], start[1]
+    lognorm = start[2] if len(start) > 2 else 0.0
+    out = {}
     with threadpool_limits(limits=1):
-        for driver in Cs:
-            st = tebd.TNState([t.copy() for t in tensors], [l.copy() for l in lams])
-            for k in range(last):
-                stochastic.qsd_step(st, mdl.jumps, dt, noise[k][0:4], fn, chi, SV_CUTOFF["split"], driver=driver)
-                if k + 1 in C_gpu0:
-                    Cs[driver][k + 1] = measure.corr_mps(st, normalize=False)[0]
+        st = tebd.TNState([t.copy() for t in tensors], [l.copy() for l in lams], lognorm)
+        for k in range(max(want)):
+            stochastic.qsd_step(st, mdl.jumps, dt, noise[k][0:4], fn, chi, SV_CUTOFF["split"], driver=driver)
+            if k + 1 in want:
+                out[k + 1] = measure.corr_mps(st, normalize=False)[0]
+    return out
+
+
+def oracle_check(tn_inputs, st_init, L, chi, dt, noise, C_gpu0, pool=None, c64start=False):
+    """{steps: (err, spread, err_density, err_nn)} for trajectory 0 at each checkpoint of C_gpu0
+    ({steps: C}).  err and spread are max |dC| / max |C|: err is the GPU against the FP64 oracle on
+    the same input and with the same truncation (chi and the split state's singular-value cutoff);
+    spread is the oracle against itself with another LAPACK SVD driver (gesvd instead of gesdd).
+    At a binding chi the kept singular vectors depend on rounding inside the SVD, and spread is the
+    scale at which two exact FP64 runs already differ.  err_density and err_nn are the GPU's
+    elementwise relative errors on the diagonal (densities) and on the first off-diagonal.
+    st_init is (tensors, lams) or (tensors, lams, lognorm); pool (a process pool started before
+    the GPU was touched) runs the drivers side by side.  With c64start each entry gains a fifth
+    figure: the oracle from the start rounded to complex64 against the oracle from the start,
+    the part of err that the precision of the stored start alone explains (at a binding chi the
+    truncation amplifies any perturbation, and this shows by how much)."""
+    jobs = oracle_jobs(st_init, L, chi, dt, noise, C_gpu0, c64start)
+    res = pool.map(_oracle_corr_run, jobs) if pool is not None else [_oracle_corr_run(j) for j in jobs]
+    return oracle_compare(C_gpu0, res, c64start)
+
+
+def oracle_jobs(st_init, L, chi, dt, noise, C_gpu0, c64start=False):
+    """The oracle runs that oracle_check compares C_gpu0 with (gesdd, gesvd and optionally the
+    complex64-rounded start), as jobs for _oracle_corr_run."""
+    want = sorted(C_gpu0)
+    drivers = ("gesdd", "gesvd", "c64start") if c64start else ("gesdd", "gesvd")
+    return [(st_init, L, chi, dt, noise, want, drv) for drv in drivers]
+
+
+def oracle_compare(C_gpu0, res, c64start=False):
+    """oracle_check's figures from the results of its oracle_jobs, in job order."""
+    drivers = ("gesdd", "gesvd", "c64start") if c64start else ("gesdd", "gesvd")
+    Cs = dict(zip(drivers, res))
     out = {}
     for n, Cg in C_gpu0.items():
         ref = Cs["gesdd"][n]
         scale = np.max(np.abs(ref))
         out[n] = (float(np.max(np.abs(Cg - ref)) / scale), float(np.max(np.abs(Cs["gesvd"][n] - ref)) / scale),
                   _elementwise(np.diag(Cg), np.diag(ref)), _elementwise(np.diag(Cg, 1), np.diag(ref, 1)))
+        if c64start:
+            out[n] = out[n] + (float(np.max(np.abs(Cs["c64start"][n] - ref)) / scale),)
     return out
 
 
@@ -267,14 +409,59 @@ def _elementwise(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))
 
 
+def _profiled_interval(api, st, noise, inner, dt, B):
+    """One output interval with kernel timing on and the chunks of a layer on the caller's stream only,
+    so that no two launches share the compute units and each HIP-event interval is one dispatch's
+    own duration.  Returns ({kernel: {total_ms, launches, avg_ms}}, bond dimensions at the start)."""
+    import torch
+    dims = [st.dims(b) for b in range(B)]
+    st.overlap(False)
+    st.prof_enable(True)
+    run_interval(api, st, noise, inner, dt)
+    torch.cuda.synchronize()
+    kt = {}
+    for kid, name in enumerate(api.K_NAMES):
+        ms, n = st.prof_query(kid)
+        kt[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0}
+    st.prof_enable(False)
+    st.overlap(True)
+    return kt, dims
+
+
+def roofline_line(api, st, kt, dims, inner, chi):
+    """Roofline of the update kernel with the largest profiled time: algorithmic flops of the items it
+    processed (every bond at its own (chi_l, chi_m, chi_r), step_work) over its summed HIP-event
+    durations, against the FP64 or FP32 matrix peak of its type."""
+    work, n_items, tmin = step_work(dims)
+    upd = ["theta", "gram", "hetrd", "vecs", "split"]
+    dom = max(upd, key=lambda k: kt[k]["total_ms"])
+    peak = PEAK["fp32"] if dom == "theta" else PEAK["fp64"]
+    flops = work[dom] * inner
+    secs = kt[dom]["total_ms"] / 1e3
+    achieved = flops / secs
+    kname, bound = bucket_kernel(dom, 2 * chi, chi, st.tuning()[0])
+    launches = max(1, kt[dom]["launches"])
+    return {"bound": bound, "kernel": kname, "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": profiled_traffic(kname),
+            "traffic_unit": "bytes per launch", "algo_flops_per_launch": flops / launches,
+            "items_per_launch": n_items * inner / launches, "avg_launch_ms": kt[dom]["avg_ms"],
+            "launches": kt[dom]["launches"], "streams": 1,
+            "basis": "profiled interval: one stream, HIP events per launch; flops of each bond's own shape"}, \
+        work, n_items, tmin
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the batch on one GPU is the measured unit)"}))
         sys.exit(2)
-    # the oracle's CPU timing runs first, before this process touches the GPU (its worker
-    # processes start from a process without GPU state)
+    # the oracle's CPU work runs in processes started before this process touches the GPU: the
+    # timing first, then a pool kept for the accuracy checks
     cpu = None if (args.no_cpu or args.calib_copy > 0) else cpu_baseline(args.L, args.chi, args.dt, args.cpu_seconds)
+    pool = None
+    if not args.no_check and args.calib_copy == 0:
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(6)
     import torch
     import tn_inputs
     from paper_2609_18841_amd import api
@@ -293,13 +480,25 @@ def main():
         print(json.dumps({"calib_copy_bytes": nb, "copies": 3}))
         return
     B, L, chi, inner, dt = args.batch, args.L, args.chi, args.inner, args.dt
-    st, init = make_state(api, tn_inputs, api.SPLIT, B, L, chi)
-    total_steps = args.warmup + args.steps
-    noise = tn_inputs.normals(7, (total_steps * inner, B * 2 * 2))
-    print(f"# bench: B={B} L={L} chi={chi} inner={inner} warmup={args.warmup} steps={args.steps}", file=sys.stderr,
-          flush=True)
+    log = lambda msg: print(f"# {msg}", file=sys.stderr, flush=True)  # noqa: E731
 
-    err = spread = None
+    cks, ck_info = None, None
+    if args.input == "physical" or not args.no_secondary:
+        t0 = time.perf_counter()
+        cks, t_ck, ck_dims = evolve_checkpoints(api, tn_inputs, L, chi, args.checkpoints, args.ck_dt, args.ck_tmax)
+        ck_info = {"count": args.checkpoints, "evolved_to_t": t_ck, "dt": args.ck_dt, "precision": "fp64",
+                   "start": "Neel", "max_bond_dim": int(max(max(d) for d in ck_dims)),
+                   "saturated_bonds": int(sum(1 for d in ck_dims[0] if d == chi)),
+                   "seconds": time.perf_counter() - t0}
+        log(f"checkpoints: {args.checkpoints} trajectories evolved to t = {t_ck:.2f}")
+    head_cks = cks if args.input == "physical" else None
+
+    bits, other_bits = args.theta_bits, 96 - args.theta_bits
+    st, init = make_state(api, tn_inputs, api.SPLIT, B, L, chi, head_cks, bits=bits)
+    total_steps = args.warmup + args.steps + 1
+    noise = tn_inputs.normals(7, (total_steps * inner, B * 2 * 2))
+    log(f"bench: B={B} L={L} chi={chi} inner={inner} warmup={args.warmup} steps={args.steps} input={args.input}")
+
     overlap = args.overlap_measure
     if overlap:
         st.measure_async_enable()
@@ -317,78 +516,117 @@ def main():
     pending = False
     for w in range(args.warmup):
         pending = interval(w * inner, pending)
-        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+        log(f"warmup {w} done")
     if pending:
         st.measure_finish()
         pending = False
+    st.stats(reset=True)
 
+    # timed region: kernel timing off, so unmasked Trotter steps replay their captured graphs
     torch.cuda.synchronize()
-    st.prof_enable(True)
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        pending = interval((args.warmup + s) * inner, pending)
-        print(f"# step {s} done", file=sys.stderr, flush=True)
+    for s_ in range(args.steps):
+        pending = interval((args.warmup + s_) * inner, pending)
+        log(f"step {s_} done")
     if pending:
         st.measure_finish()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     updates = args.steps * inner * (L - 1) * B
     value = updates / el
-    kt = {}
-    for kid, name in enumerate(api.K_NAMES):
-        ms, n = st.prof_query(kid)
-        kt[name] = {"total_ms": ms, "launches": n, "busy_ms": st.prof_busy(kid)}
-    st.prof_enable(False)
+    fb_items, mgs_items = st.stats()
 
-    # Roofline of the dominant update kernel (FLOP-bound, FP64 or FP32 peak by kernel type).  The
-    # chunks of a layer run on two streams (when a layer spans more than one chunk), so two
-    # launches of the same kernel can run at once and each one's duration covers both; the
-    # kernel's rate is its algorithmic work over the wall time during which any launch of it
-    # runs (union of the launch intervals, HIP events on both streams).  busy_ms_per_launch is
-    # that time per launch, comparable with the union of dispatch intervals in the committed
-    # rocprofv3 kernel trace; avg_launch_ms is the plain per-launch duration.
-    fl = algo_flops(n=2 * chi, m=2 * chi, chim=chi, k=chi)
-    upd_kernels = ["theta", "gram", "hetrd", "vecs", "split"]
-    dom = max(upd_kernels, key=lambda k: kt[k]["busy_ms"])
-    peak = PEAK["fp32"] if dom in ("theta", "split") else PEAK["fp64"]
-    launches = max(1, kt[dom]["launches"])
-    items_per_launch = updates / launches
-    busy_s = kt[dom]["busy_ms"] / 1e3
-    achieved = fl[dom] * updates / busy_s if busy_s > 0 else 0.0
-    kname, bound = bucket_kernel(dom, 2 * chi, chi, st.tuning()[0])
-    roof = {"bound": bound, "kernel": kname,
-            "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": profiled_traffic(kname), "traffic_unit": "bytes per launch",
-            "algo_flops_per_update": fl[dom], "items_per_launch": items_per_launch,
-            "busy_ms_per_launch": kt[dom]["busy_ms"] / launches,
-            "avg_launch_ms": kt[dom]["total_ms"] / launches,
-            "streams": 2 if kt[dom]["total_ms"] > 1.2 * kt[dom]["busy_ms"] else 1}
+    # roofline from a separate profiled interval (one stream, HIP events), after the timed region
+    kt, dims0 = _profiled_interval(api, st, noise[(args.warmup + args.steps) * inner:], inner, dt, B)
+    dims1 = [st.dims(b) for b in range(B)]
+    changed = float(np.mean([np.mean(np.asarray(a) != np.asarray(b)) for a, b in zip(dims0, dims1)]))
+    roof, work, n_items, tmin = roofline_line(api, st, kt, dims0, inner, chi)
+    roof["bond_dims_changed_during_interval"] = changed
+    interval_ms = sum(v["total_ms"] for k, v in kt.items())
+    pm = path_model(2, chi)
+    t_min_avg = tmin / n_items
+    path_roof = {"flops_per_update_square": pm["flops_per_update"], "t_min_us_square": pm["t_min_us"],
+                 "t_min_us_per_update": t_min_avg * 1e6, "bound_updates_per_s": 1.0 / t_min_avg,
+                 "frac": value * t_min_avg,
+                 "frac_updates_only": value * t_min_avg / max(1e-9, 1.0 - kt["measure"]["total_ms"] / interval_ms),
+                 "measure_share_of_kernel_time": kt["measure"]["total_ms"] / interval_ms,
+                 "basis": "value (with the measurement sweep) against the flop model summed over each bond's shape"}
+    del st
+    torch.cuda.empty_cache()
 
-    # plain per-instance FP64 GPU path (one instance per call), same workload shape
+    # plain per-instance FP64 GPU path (one instance per call), same input
     plain = None
     if not args.no_plain:
-        del st
-        torch.cuda.empty_cache()
-        pst, _ = make_state(api, tn_inputs, api.FP64, 1, L, chi)
-        pst.tebd_step(dt, order=1)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for i in range(args.plain_instances):
-            pst.tebd_step(dt, order=1)
-            pst.apply_jumps(api.MODE_QSD, dt, noise[i][:4], api.NOISE_GAUSS)
-        torch.cuda.synchronize()
-        pel = time.perf_counter() - t1
-        pv = args.plain_instances * (L - 1) / pel
-        plain = {"value": pv, "unit": "two-site updates/s", "precision": "fp64",
-                 "instances_timed": args.plain_instances, "speedup_split_batched": value / pv}
+        pst, _ = make_state(api, tn_inputs, api.FP64, 1, L, chi, head_cks)
+        run_interval(api, pst, noise[:1, :4], 1, dt, measure=False)
+        rates = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            run_interval(api, pst, noise[r * args.plain_steps:(r + 1) * args.plain_steps, :4], args.plain_steps, dt,
+                         measure=False)
+            torch.cuda.synchronize()
+            rates.append(args.plain_steps * (L - 1) / (time.perf_counter() - t1))
+        pv = float(np.mean(rates))
+        plain = {"value": pv, "unit": "two-site updates/s", "precision": "fp64", "batch": 1,
+                 "steps_timed": 3 * args.plain_steps, "runs": rates, "speedup_split_batched": value / pv}
         del pst
         torch.cuda.empty_cache()
+        log("plain fp64 done")
 
-    checks = None
-    if not args.no_check:
-        # trajectory 0 of a two-trajectory batch against the oracle after one output interval and
-        # after check_steps Trotter steps, on the same noise
-        cst, init2 = make_state(api, tn_inputs, api.SPLIT, 2, L, chi)
+    # batched FP64 at the full batch: separates the batching gain from the precision gain
+    fp64b = None
+    if args.fp64_batched_steps > 0:
+        fst, _ = make_state(api, tn_inputs, api.FP64, B, L, chi, head_cks)
+        run_interval(api, fst, noise[:1], 1, dt, measure=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_interval(api, fst, noise[1:1 + args.fp64_batched_steps], args.fp64_batched_steps, dt, measure=False)
+        torch.cuda.synchronize()
+        fv = args.fp64_batched_steps * (L - 1) * B / (time.perf_counter() - t1)
+        fp64b = {"value": fv, "unit": "two-site updates/s", "precision": "fp64", "batch": B,
+                 "steps_timed": args.fp64_batched_steps, "measurement": "none (Trotter steps and noise only)",
+                 "split_over_fp64_batched": value / fv}
+        del fst
+        torch.cuda.empty_cache()
+        log("batched fp64 done")
+
+    def short_run(start_cks, b, n_int=2):
+        """updates/s of a split batch over n_int output intervals after one untimed interval, and the
+        eigensolver route counts of the timed ones"""
+        sst, _ = make_state(api, tn_inputs, api.SPLIT, B, L, chi, start_cks, bits=b)
+        run_interval(api, sst, noise[:inner], inner, dt)
+        sst.stats(reset=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for r in range(n_int):
+            run_interval(api, sst, noise[(r + 1) * inner:(r + 2) * inner], inner, dt)
+        torch.cuda.synchronize()
+        v = n_int * inner * (L - 1) * B / (time.perf_counter() - t1)
+        f, m = sst.stats()
+        sst.close()
+        del sst
+        torch.cuda.empty_cache()
+        return {"value": v, "unit": "two-site updates/s", "steps": n_int, "ql_fallback_items": f,
+                "reorthogonalized_items": m, "updates": n_int * inner * (L - 1) * B}
+
+    # the other Theta precision on the headline input
+    other = dict(short_run(head_cks, other_bits), theta_bits=other_bits)
+    log(f"theta bits {other_bits} done")
+
+    # secondary input: the geometric-spectrum tensors (or the checkpoints when they are not the headline)
+    second = None
+    if not args.no_secondary:
+        alt = None if head_cks is not None else cks
+        second = {"input": "synthetic geometric spectrum" if alt is None else "physical checkpoints",
+                  "theta_bits": bits, **short_run(alt, bits),
+                  "other_theta_bits": dict(short_run(alt, other_bits), theta_bits=other_bits)}
+        log("secondary input done")
+
+    def gpu_trajectory(start_cks, b):
+        """trajectory 0 of a two-trajectory split batch: C after one output interval and after
+        check_steps Trotter steps, on the noise the oracle replays"""
+        cst, init2 = make_state(api, tn_inputs, api.SPLIT, 2, L, chi, start_cks, bits=b)
         nlong = max(inner, args.check_steps)
         nz = tn_inputs.normals(7, (nlong, B * 2 * 2))[:, :2 * 2 * 2]
         Cg = {}
@@ -397,27 +635,65 @@ def main():
             cst.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
             if k + 1 in (inner, nlong):
                 Cg[k + 1] = cst.measure_corr(normalize=0, each=True)[2][0]
-        checks = oracle_check(tn_inputs, init2, L, chi, dt, nz, Cg)
-        err, spread = checks[inner][:2]
-        del cst
+        cst.close()
+        return init2, nz, Cg
 
-    pm = path_model(2, chi)
+    def summarize(checks):
+        return {str(n): dict(zip(["err_vs_fp64_oracle", "oracle_driver_spread", "density_elementwise",
+                                  "nearest_neighbour_elementwise", "oracle_c64_start_spread"], v))
+                for n, v in sorted(checks.items())}
+
+    checks = checks2 = checks_o = checks2_o = None
+    err = spread = None
+    if not args.no_check:
+        # both Theta precisions on each input, against the same oracle runs
+        starts = [head_cks] + ([None if head_cks is not None else cks] if second is not None else [])
+        runs = []
+        for sc in starts:
+            init_a, nz_a, Cg_a = gpu_trajectory(sc, bits)
+            _, _, Cg_b = gpu_trajectory(sc, other_bits)
+            runs.append((init_a, nz_a, Cg_a, Cg_b))
+        # every oracle run of both inputs side by side in the pool
+        jobs = [oracle_jobs(i, L, chi, dt, z, c, c64start=True) for i, z, c, _ in runs]
+        flat = pool.map(_oracle_corr_run, [j for js in jobs for j in js])
+        outs = [(oracle_compare(c, flat[3 * r:3 * r + 3], c64start=True),
+                 oracle_compare(c2, flat[3 * r:3 * r + 3], c64start=True)) for r, (_, _, c, c2) in enumerate(runs)]
+        checks, checks_o = outs[0]
+        if len(outs) > 1:
+            checks2, checks2_o = outs[1]
+        err, spread = checks[inner][:2]
+        log("oracle check done")
+    if pool is not None:
+        pool.close()
+        pool.join()
+
+    workload = (f"QSD trajectory batch B={B}, L={L}, chi={chi}, dt={dt}, {inner} Trotter steps + noise per "
+                f"output, 1 measurement of C per output; split precision; start: "
+                + ("FP64-evolved checkpoints" if head_cks is not None else "geometric-spectrum tensors"))
     res = {
         "metric": "two-site TEBD updates/sec (batched trajectories, L=64 chi=64) vs plain, at stated err",
         "value": value, "unit": "two-site updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64-contract/f64-svd", "data": "synthetic",
-        "config": {"workload": f"QSD trajectory batch B={B}, L={L}, chi={chi}, dt={dt}, {inner} Trotter steps + "
-                               f"noise per output, 1 measurement of C per output; split precision",
-                   "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner,
-                   "measurement": "beside the next interval's steps (snapshot)" if overlap else "synchronous"},
-        "roofline": roof, "path_roofline": dict(pm, frac=value * pm["t_min_us"] * 1e-6),
-        "cpu_baseline": cpu, "plain_fp64": plain,
-        "err_vs_fp64_oracle": err, "oracle_driver_spread": spread,
-        "err_by_steps": None if checks is None else {
-            str(n): {"err_vs_fp64_oracle": e, "oracle_driver_spread": sp, "density_elementwise": ed,
-                     "nearest_neighbour_elementwise": en} for n, (e, sp, ed, en) in sorted(checks.items())},
-        "kernel_ms": kt,
+        "dtype": "c64-store/f64-contract/f64-svd" if bits == 64 else "c64-store/f32-contract/f64-svd",
+        "data": "synthetic",
+        "config": {"workload": workload, "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner,
+                   "input": args.input, "checkpoints": ck_info, "theta_bits": bits,
+                   "measurement": "beside the next interval's steps (snapshot)" if overlap else "synchronous",
+                   "timing": "kernel timing off; captured HIP graphs replay the Trotter steps"},
+        "roofline": roof, "path_roofline": path_roof,
+        "cpu_baseline": cpu, "plain_fp64": plain, "fp64_batched": fp64b, "secondary_input": second,
+        "eigensolver_routes": {"ql_fallback_items": fb_items, "reorthogonalized_items": mgs_items,
+                               "updates": updates},
+        "err_vs_fp64_oracle": err, "oracle_driver_spread": spread, "err_tolerance": ERR_TOLERANCE,
+        "err_within_tolerance": None if checks is None else {
+            str(n): v[0] <= ERR_TOLERANCE for n, v in sorted(checks.items())},
+        "err_by_steps": None if checks is None else summarize(checks),
+        "secondary_err_by_steps": None if checks2 is None else summarize(checks2),
+        "secondary_err_within_tolerance": None if checks2 is None else {
+            str(n): v[0] <= ERR_TOLERANCE for n, v in sorted(checks2.items())},
+        "other_theta_bits": dict(other, err_by_steps=None if checks_o is None else summarize(checks_o),
+                                 secondary_err_by_steps=None if checks2_o is None else summarize(checks2_o)),
+        "kernel_ms_profiled_interval": kt,
     }
     print(json.dumps(res))
 

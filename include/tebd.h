@@ -48,8 +48,10 @@ extern "C" {
 #define TN_KIND_PURIFIED 2
 
 #define TN_FP64  0   /* all contractions and storage in complex128 */
-#define TN_SPLIT 1   /* complex64 storage and MFMA contractions (FP32 accumulate);
-                        Gram, eigensolver, weights, norms and log-norms in FP64 */
+#define TN_SPLIT 1   /* complex64 storage of the site tensors; Theta and the measurement
+                        sweep on the FP32 matrix cores (FP32 sums per 8-deep k-chunk, added in
+                        FP64); Theta~, Gram, eigensolver, split, weights, norms and log-norms in
+                        FP64 */
 
 #define TN_MODE_QT    0  /* quantum-trajectory jumps, Sec. 4.1 */
 #define TN_MODE_QSD   1  /* quantum-state-diffusion noise, Sec. 4.2 */
@@ -254,6 +256,18 @@ int tn_graph_enable(void* s, int on);
  * stream; on = 1 (the default) allows the overlap.  Returns TN_OK or TN_EINVAL (null handle). */
 int tn_overlap(void* s, int on);
 
+/* ---- precision of the Theta contraction ---------------------------------- */
+
+/* TN_SPLIT forms Theta~ = G (B_b B_{b+1}) (eq. Theta) by default (bits = 32) on the FP32 matrix
+ * cores from the complex64 site tensors, with FP32 sums per 8-deep k-chunk added in FP64.  bits =
+ * 64 forms it on the FP64 matrix cores instead, where the products of complex64 values are exact
+ * and only the FP64 sums round; the split path's error is then that of its complex64 storage.
+ * Either way Theta~ is kept in FP64 for the Gram matrix and the split, and the gate is applied in
+ * FP64.  The choice matters where the truncation at a binding chi amplifies rounding (saturated
+ * states from physical evolution).  TN_FP64 always contracts in FP64 (bits = 32 is refused
+ * there).  Results are deterministic for either choice.  Returns TN_OK or TN_EINVAL. */
+int tn_theta_precision(void* s, int bits);
+
 /* ---- Trotter schedule ----------------------------------------------------- */
 
 /* Selects how tebd_step applies a Trotter step (both give the same Trotter product, Sec. 2.3):
@@ -270,6 +284,17 @@ int tn_overlap(void* s, int on);
  *   about 2(L-1) (order 1) or 4(L-1) (order 2) dependent launch sequences per step.
  * Returns TN_OK or TN_EINVAL (null handle, unknown schedule). */
 int tn_schedule(void* s, int schedule);
+
+/* ---- eigensolver path counters ------------------------------------------- */
+
+/* Split precision with n <= 128 and chi <= 64 takes the tridiagonal eigenvectors from bisection
+ * and twisted factorization; an item whose kept eigenvalues are closer than 1e-11 lambda_max (a
+ * degenerate multiplet) or whose factorization fails goes to the implicit-QL fallback, and an
+ * item whose kept eigenvalues are closer than 1e-8 lambda_max has its vectors re-orthogonalized.
+ * tn_stats reports how many two-site updates took each route since mps_alloc or the last reset
+ * (either output may be NULL); reset = 1 zeroes both counts after reading them.  Other precisions
+ * and shapes count nothing.  Returns TN_OK, TN_EINVAL (null handle) or TN_EHIP. */
+int tn_stats(void* s, int reset, long long* ql_fallback_items, long long* reorthogonalized_items);
 
 /* ---- kernel timing (HIP events on the library stream) -------------------- */
 #define TN_K_THETA   0  /* Theta formation + gate */

@@ -11,7 +11,7 @@ EXPORTS = [
     "mps_last_error", "mps_instance_tensor_capacity", "mps_instance_lambda_capacity",
     "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_overlap", "tn_schedule", "tn_prof_enable",
     "tn_prof_query", "tn_prof_busy", "tn_measure_async_bytes", "tn_measure_async_enable", "measure_corr_start",
-    "measure_corr_finish", "measure_corr_noalloc",
+    "measure_corr_finish", "measure_corr_noalloc", "tn_stats", "tn_theta_precision",
 ]
 
 
@@ -59,6 +59,10 @@ def load():
     lib.measure_corr_start.argtypes = [vp, ctypes.c_int]
     lib.measure_corr_finish.restype = ctypes.c_int
     lib.measure_corr_finish.argtypes = [vp, dp, dp, dp, dp]
+    lib.tn_theta_precision.restype = ctypes.c_int
+    lib.tn_theta_precision.argtypes = [vp, ctypes.c_int]
+    lib.tn_stats.restype = ctypes.c_int
+    lib.tn_stats.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     lib.measure_corr_noalloc.restype = ctypes.c_int
     lib.measure_corr_noalloc.argtypes = [vp, ctypes.c_int, dp, dp, dp, dp]
     lib.mps_free.restype = ctypes.c_int

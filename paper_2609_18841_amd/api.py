@@ -230,6 +230,23 @@ class State:
             lo += dims[b + 1]
         return tensors, lams, float(ln[0]), float(tr[0])
 
+    def dims(self, inst):
+        """Bond dimensions of instance inst (L + 1 ints, dims[0] = dims[L] = 1)."""
+        d = np.zeros(self.L + 1, dtype=np.int32)
+        _check(self.lib.mps_get_instance(self.h, inst, _ip(d), None, None, None, None))
+        return d
+
+    def lams(self, inst):
+        """Bond weights of instance inst: a list of L - 1 arrays (bond b holds dims[b + 1] values)."""
+        d = np.zeros(self.L + 1, dtype=np.int32)
+        lam = np.zeros(self.lcap)
+        _check(self.lib.mps_get_instance(self.h, inst, _ip(d), None, _dp(lam), None, None))
+        out, lo = [], 0
+        for b in range(self.L - 1):
+            out.append(lam[lo:lo + d[b + 1]].copy())
+            lo += d[b + 1]
+        return out
+
     def set_instance(self, inst, tensors, lams, lognorm=0.0):
         dims = np.array([1] + [t.shape[2] for t in tensors], dtype=np.int32)
         flat = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.complex128).reshape(-1) for t in tensors]))
@@ -249,6 +266,13 @@ class State:
         return 2
 
     # ---- timing
+    def stats(self, reset=False):
+        """(items sent to the implicit-QL fallback, items re-orthogonalized) since mps_alloc or the
+        last reset (split precision, n <= 128, chi <= 64)."""
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(self.lib.tn_stats(self.h, 1 if reset else 0, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def prof_enable(self, on=True):
         _check(self.lib.tn_prof_enable(self.h, 1 if on else 0))
 
@@ -266,6 +290,10 @@ class State:
     def overlap(self, on=True):
         """Allow (default) or forbid running the chunks of a layer on two streams."""
         _check(self.lib.tn_overlap(self.h, 1 if on else 0))
+
+    def theta_precision(self, bits):
+        """Split mode: form Theta on the FP32 (32, default) or the FP64 (64) matrix cores."""
+        _check(self.lib.tn_theta_precision(self.h, int(bits)))
 
     def schedule(self, sched):
         """SCHED_LAYER (layer-parallel Hastings form) or SCHED_SWEEP (sequential sweep with the

@@ -79,8 +79,9 @@ struct DevWork {
     const double2* gates;        // gate table for this layer: [bond] stride gstride
     int gstride;
     int mmax, nmax;              // max Theta rows / cols
-    size_t theta_stride;         // elements (T) per item
-    void* theta;                 // items * theta_stride (T)
+    size_t theta_stride;         // elements per item
+    void* theta;                 // items * theta_stride complex128 (Theta~)
+    int theta64;                 // 1: Theta~ contracted on the FP64 matrix cores (always in FP64 mode)
     double2* gram;               // items * nmax * nmax
     double2* refl;               // items * nmax * nmax   (Householder vectors)
     double2* tau;                // items * nmax
@@ -99,6 +100,7 @@ struct DevWork {
     double2* zscratch;           // items * nmax * vld  (global eigenvector scratch, large n)
     double2* pscratch;           // items * nmax*(nmax+1)/2 (packed matrix for large n)
     int* flags;                  // 1 word
+    unsigned long long* counters;  // [0] items sent to the logged-QL fallback, [1] items re-orthogonalized
     int* gsz;                    // items  size of the Hermitian eigenproblem (n, or m on the QR route)
     double2* qra;                // items * nmax * nmax  Householder QR of Theta^+ (FP64 mode, wide items)
     double2* qtau;               // items * nmax

@@ -1,6 +1,7 @@
 // Block-level complex GEMM core used by the Theta, Gram, split and measurement
-// kernels.  Complex64 operands run on the FP32 matrix cores (block_gemm_mfma_c32), complex128
-// operands on the FP64 matrix cores (block_gemm_mfma_c64).  One 256-thread workgroup computes a
+// kernels.  Complex64 operands run on the FP32 matrix cores (block_gemm_mfma_c32, FP32 sums per
+// k-chunk added in FP64), complex128 operands on the FP64 matrix cores (block_gemm_mfma_c64).
+// Both hand FP64 sums (double2) to the store functor.  One 256-thread workgroup computes a
 // 64 x 64 tile of
 //     C(m, n) = sum_k A(m, k) * B(k, n)
 // where A and B are supplied by load functors (so transposition, conjugation,
@@ -36,28 +37,41 @@ __device__ __forceinline__ void gemm_stage(int M, int N, int K, int m0, int n0, 
     }
 }
 
+typedef double gemm_d4 __attribute__((ext_vector_type(4)));
+
 // Complex64 tiles on the matrix cores: each of the 4 waves owns a 32 x 32 quarter of the
 // 64 x 64 tile as 2 x 2 blocks of 16 x 16; a k-step of 4 is four real MFMA 16x16x4 f32
-// products per block (re*re, -im*im into the real part, re*im, im*re into the imaginary part),
-// accumulated in FP32.  Operand layouts: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// accumulator element r of lane l is C[4*(l/16) + r][l%16].
+// products per block (re*re, -im*im into the real part, re*im, im*re into the imaginary part).
+// The products of one staged k-chunk (BK deep) accumulate in FP32 on the matrix cores, and each
+// chunk's sums are added to FP64 accumulators: a K-deep sum then rounds like BK-deep FP32 sums
+// added exactly, about sqrt(K / BK) times less than one K-deep FP32 accumulation.  The store
+// functor receives the FP64 sums.  Operand layouts: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element r of lane l is C[4*(l/16) + r][l%16].
 template <bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
 __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
                                                     float2* As, float2* Bs) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-    gemm_f4 cr[2][2], ci[2][2];
+    gemm_d4 dr[2][2], di[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            cr[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
-            ci[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+            dr[a][b] = gemm_d4{0.0, 0.0, 0.0, 0.0};
+            di[a][b] = gemm_d4{0.0, 0.0, 0.0, 0.0};
         }
     for (int k0 = 0; k0 < K; k0 += BK) {
         gemm_stage<float2, A_KFAST, B_NFAST, BK>(M, N, K, m0, n0, k0, la, lb, As, Bs);
         __syncthreads();
+        gemm_f4 cr[2][2], ci[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cr[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+                ci[a][b] = gemm_f4{0.f, 0.f, 0.f, 0.f};
+            }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             float2 av[2], bv[2];
@@ -76,6 +90,15 @@ __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0,
                 }
         }
         __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    dr[a][b][r] += (double)cr[a][b][r];
+                    di[a][b][r] += (double)ci[a][b][r];
+                }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -84,11 +107,10 @@ __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int gm = m0 + wm + 16 * a + 4 * lk + r, gn = n0 + wn + 16 * b + li;
-                if (gm < M && gn < N) sc(gm, gn, make_float2(cr[a][b][r], ci[a][b][r]));
+                if (gm < M && gn < N) sc(gm, gn, make_double2(dr[a][b][r], di[a][b][r]));
             }
 }
 
-typedef double gemm_d4 __attribute__((ext_vector_type(4)));
 
 // Complex128 tiles on the FP64 matrix cores, the same wave and block split as the FP32 core: a
 // k-step of 4 is four real MFMA 16x16x4 f64 products per 16 x 16 block, accumulated in FP64.

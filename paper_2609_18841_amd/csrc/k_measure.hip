@@ -45,7 +45,7 @@ __global__ __launch_bounds__(NT) void k_env_right_a(DevState s, MeasWork mw, int
         M, N, K, tm * 64, tn * 64,
         [&](int r, int c) { return P[(size_t)r * K + c]; },
         [&](int c, int cp) { return R[(size_t)cp * K + c]; },
-        [&](int r, int cp, T v) { U[(size_t)r * N + cp] = v; }, As, Bs);
+        [&](int r, int cp, double2 v) { U[(size_t)r * N + cp] = cconv<T>(v); }, As, Bs);
 }
 
 // R_j[a'][a] = sum_{(p,c')} conj(B[a'][(p,c')]) U[a][(p,c')]
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(NT) void k_env_right_b(DevState s, MeasWork mw, int
         M, M, K, tm * 64, tn * 64,
         [&](int ap, int k) { return cconj(Bm[(size_t)ap * K + k]); },
         [&](int k, int a) { return U[(size_t)a * K + k]; },
-        [&](int ap, int a, T v) { R[(size_t)ap * M + a] = v; }, As, Bs);
+        [&](int ap, int a, double2 v) { R[(size_t)ap * M + a] = cconv<T>(v); }, As, Bs);
 }
 
 // ---------------------------------------------------------------- left sweep pieces
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(NT) void k_meas_y(DevState s, MeasWork mw, int j, i
         M, N, K, tm * 64, tn * 64,
         [&](int ap, int a) { return X[(size_t)ap * K + a]; },
         [&](int a, int pc) { return Bm[(size_t)a * N + pc]; },
-        [&](int ap, int pc, T v) { Y[(size_t)ap * N + pc] = v; }, As, Bs);
+        [&](int ap, int pc, double2 v) { Y[(size_t)ap * N + pc] = cconv<T>(v); }, As, Bs);
 }
 
 // W[(a',p')][c] = sum_c' conj(B[(a',p')][c']) R_{j+1}[c'][c]
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(NT) void k_meas_w(DevState s, MeasWork mw, int j, i
         M, N, K, tm * 64, tn * 64,
         [&](int r, int cp) { return cconj(P[(size_t)r * K + cp]); },
         [&](int cp, int c) { return R[(size_t)cp * N + c]; },
-        [&](int r, int c, T v) { W[(size_t)r * N + c] = v; }, As, Bs);
+        [&](int r, int c, double2 v) { W[(size_t)r * N + c] = cconv<T>(v); }, As, Bs);
 }
 
 // value = sum_{n',n} O[n'][n] sum_k sum_{a',c} Y[a'][(n,k)][c] W[(a',(n',k))][c]   (FP64 accumulate)
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NT) void k_meas_upd(DevState s, MeasWork mw, int j,
                 int ap = kk / dk, k = kk % dk;
                 return Y[((size_t)ap * d + k) * chir + c];
             },
-            [&](int cp, int c, T v) { out[(size_t)cp * chir + c] = v; }, As, Bs);
+            [&](int cp, int c, double2 v) { out[(size_t)cp * chir + c] = cconv<T>(v); }, As, Bs);
     } else {
         const bool fsign = slot < nslot_x;
         const int K = chil * d;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_meas_upd(DevState s, MeasWork mw, int j,
                 return v;
             },
             [&](int kk, int c) { return Y[(size_t)kk * chir + c]; },
-            [&](int cp, int c, T v) { out[(size_t)cp * chir + c] = v; }, As, Bs);
+            [&](int cp, int c, double2 v) { out[(size_t)cp * chir + c] = cconv<T>(v); }, As, Bs);
     }
 }
 

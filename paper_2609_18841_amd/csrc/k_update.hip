@@ -62,22 +62,26 @@ __device__ __forceinline__ bool item_dims(const DevState& s, const DevWork& w, i
 }
 
 // ------------------------------------------------------------------ Theta
-template <class T>
+// T: storage type of the site tensors.  TC: operand type of the contraction, complex64 on the FP32
+// matrix cores (FP32 sums per 8-deep k-chunk, added in FP64) or complex128 on the FP64 ones (the
+// products of complex64 values are exact there).  Theta~ goes to the workspace in complex128 in
+// both cases, so it is not rounded again before the Gram matrix and the split read it.
+template <class T, class TC>
 __global__ __launch_bounds__(NT) void k_theta(DevState s, DevWork w, int tiles_n) {
-    __shared__ T As[8 * 64], Bs[8 * 64];
+    __shared__ TC As[8 * 64], Bs[8 * 64];
     ItemDims d;
     if (!item_dims(s, w, blockIdx.y, d)) return;
     int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.m || tn * 64 >= d.n) return;
     const T* P = site_ptr<T>(s, d.b, d.bond);
     const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
-    T* out = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    double2* out = reinterpret_cast<double2*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
     const int K = d.chim, n = d.n;
-    block_gemm<T, true, true, 8>(
+    block_gemm<TC, true, true, 8>(
         d.m, d.n, K, tm * 64, tn * 64,
-        [&](int r, int k) { return P[(size_t)r * K + k]; },
-        [&](int k, int c) { return Q[(size_t)k * n + c]; },
-        [&](int r, int c, T v) { out[(size_t)r * n + c] = v; }, As, Bs);
+        [&](int r, int k) { return cconv<TC>(P[(size_t)r * K + k]); },
+        [&](int k, int c) { return cconv<TC>(Q[(size_t)k * n + c]); },
+        [&](int r, int c, double2 v) { out[(size_t)r * n + c] = v; }, As, Bs);
 }
 
 // Theta~ = G (x) (B_bond . B_{bond+1}) in one pass (eq. Theta): the GEMM runs over a virtual
@@ -85,55 +89,55 @@ __global__ __launch_bounds__(NT) void k_theta(DevState s, DevWork w, int tiles_n
 // V -> q = (V % 64) / cw, c = (V / 64) cw + (V % 64) % cw), so the d_l d_r entries that the gate
 // mixes, rows (a, p) and columns (q, c), all land in one tile.  The tile is staged in LDS and
 // the gate applied on the way to memory.
-template <class T, int DM>
+template <class T, class TC, int DM>
 __global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int tiles_n) {
-    // the output tile reuses the operand staging space: block_gemm ends its k loop with a
+    // the output tile (FP64) reuses the operand staging space: block_gemm ends its k loop with a
     // barrier, after which the staging buffers are dead
-    __shared__ T smem[64 * 64];
-    __shared__ T G[256];
-    T* As = smem;
-    T* Bs = smem + 8 * 64;
-    T* tile = smem;
+    __shared__ double2 smem[64 * 64];
+    __shared__ double2 G[256];
+    TC* As = reinterpret_cast<TC*>(smem);
+    TC* Bs = As + 8 * 64;
+    double2* tile = smem;
     ItemDims d;
     if (!item_dims(s, w, blockIdx.y, d)) return;
     const int dl = d.dl, dr = d.dr, D = dl * dr, cw = 64 / dr, chir = d.chir, n = d.n;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.m || tn * cw >= chir) return;
-    // the gate is staged as G - 1 and the identity part added exactly: a Trotter gate is
-    // 1 + O(dt), and rounding G itself to the working precision would perturb the generator by
-    // ~eps/dt coherently at every step, while rounding G - 1 perturbs it by ~eps |h|
+    // the gate is staged as G - 1 and the identity part added exactly, in FP64: a Trotter gate is
+    // 1 + O(dt), and rounding G itself to FP32 would perturb the generator by ~eps/dt coherently
+    // at every step
     const double2* g = w.gates + (size_t)d.bond * w.gstride;
     for (int e = threadIdx.x; e < D * D; e += NT) {
         double2 ge = g[e];
         if (e / D == e % D) ge.x -= 1.0;
-        G[e] = cconv<T>(ge);
+        G[e] = ge;
     }
     const T* P = site_ptr<T>(s, d.b, d.bond);
     const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
-    T* out = reinterpret_cast<T*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
+    double2* out = reinterpret_cast<double2*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
     const int K = d.chim, m0 = tm * 64;
-    block_gemm<T, true, true, 8>(
+    block_gemm<TC, true, true, 8>(
         d.m, tiles_n * 64, K, m0, tn * 64,
-        [&](int r, int k) { return P[(size_t)r * K + k]; },
+        [&](int r, int k) { return cconv<TC>(P[(size_t)r * K + k]); },
         [&](int k, int V) {
             const int loc = V & 63, q = loc / cw, c = (V >> 6) * cw + loc % cw;
-            return c < chir ? Q[(size_t)k * n + q * chir + c] : czero<T>();
+            return c < chir ? cconv<TC>(Q[(size_t)k * n + q * chir + c]) : czero<TC>();
         },
-        [&](int r, int V, T v) { tile[(r - m0) * 64 + (V & 63)] = v; }, As, Bs);
+        [&](int r, int V, double2 v) { tile[(r - m0) * 64 + (V & 63)] = v; }, As, Bs);
     __syncthreads();
     const int npair = (64 / dl) * cw;
     for (int e = threadIdx.x; e < npair; e += NT) {
         const int al = e / cw, cl = e % cw, c = tn * cw + cl;
         const int r0 = m0 + al * dl;
         if (c >= chir || r0 >= d.m) continue;
-        T v[DM];
+        double2 v[DM];
 #pragma unroll
         for (int x = 0; x < DM; ++x)
             if (x < D) v[x] = tile[(al * dl + x / dr) * 64 + (x % dr) * cw + cl];
 #pragma unroll
         for (int o = 0; o < DM; ++o) {
             if (o < D) {
-                T acc = v[o];
+                double2 acc = v[o];
 #pragma unroll
                 for (int x = 0; x < DM; ++x)
                     if (x < D) cfma(acc, G[o * D + x], v[x]);
@@ -1053,6 +1057,7 @@ __device__ __forceinline__ void steqr_item(const DevState& s, const DevWork& w, 
     ItemDims dm;
     if (!item_dims(s, w, j, dm)) return;
     if (w.fb && w.fb[j] != 1) return;  // eigenvectors come from the bisection path
+    if (w.fb) atomicAdd(&w.counters[0], 1ull);
     const int n = w.gsz[j];
     double* gd = w.dd + (size_t)j * w.nmax;
     double* ge = w.ee + (size_t)j * w.nmax;
@@ -1154,8 +1159,9 @@ __global__ __launch_bounds__(QL_TPB) void k_steqr(DevState s, DevWork w) {
 #define QL_FB_BLOCKS 16
 __global__ __launch_bounds__(QL_TPB) void k_steqr_fb(DevState s, DevWork w) {
     __shared__ double sdd[QL_LDS_N * QL_TPB], see[QL_LDS_N * QL_TPB];
-    for (int j = blockIdx.x * QL_TPB + threadIdx.x; j < w.nitems; j += gridDim.x * QL_TPB)
+    for (int j = blockIdx.x * QL_TPB + threadIdx.x; j < w.nitems; j += gridDim.x * QL_TPB) {
         steqr_item<true>(s, w, j, threadIdx.x, sdd, see);
+    }
 }
 
 // ------------------------------------------------------------------ selection and truncation
@@ -1691,10 +1697,13 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
 // factorization that overflows, send the item to the logged QL path (k_steqr, k_select,
 // k_vecs_fast run on those items only): fb = 1.  Computed eigenvectors are orthogonal to about
 // eps lambda_max / gap, so the Gram-Schmidt pass runs only when some kept gap is below
-// 1e-6 lambda_max (fb = 2); otherwise fb = 0.
+// 1e-8 lambda_max (fb = 2); otherwise fb = 0.  Above that gap the loss of orthogonality stays
+// near 1e-8, below the rounding of the complex64 storage the vectors go to (B_{b+1} = V^+);
+// most bulk bonds of a saturated physical state keep several eigenvalues below 1e-6 lambda_max,
+// so a 1e-6 threshold would send nearly every item through the pass.
 #define BS_MAXIT 64
 #define TV_TIGHT 1e-11
-#define TV_SEP 1e-6
+#define TV_SEP 1e-8
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -1817,6 +1826,7 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
     if (w.fb[j] == 1) return;
     const int n = w.gsz[j], tid = threadIdx.x, k = w.kout[j];
     const bool mgs = w.fb[j] == 2;
+    if (mgs && tid == 0) atomicAdd(&w.counters[1], 1ull);
     const double* gd = w.dd + (size_t)j * w.nmax;
     const double* ge = w.ee + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) {
@@ -1930,9 +1940,9 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
 
 // ------------------------------------------------------------------ Hastings split
 // B_bond = Theta~ V / s on the FP64 matrix cores in both precisions: V is the FP64 eigenvector
-// matrix and Theta~ enters as stored (complex64 in split mode, converted exactly), so the only
-// rounding of the split is the final store.  FP32 products here would round V and accumulate
-// 2 n terms in FP32 at every update, a per-update error several times that of the store.
+// matrix and Theta~ the FP64 workspace copy, so the only rounding of the split is the final
+// store.  FP32 products here would round V and Theta~ at every update, a per-update error
+// several times that of the store.
 template <class T>
 __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n, double* glog, double* gwt) {
     __shared__ double2 As[8 * 64], Bs[8 * 64];
@@ -1950,7 +1960,7 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     if (tm * 64 >= d.m || tn * 64 >= k) return;
     typedef typename real_of<T>::type R;
-    const T* th = reinterpret_cast<const T*>(w.theta) + (size_t)j * w.theta_stride;
+    const double2* th = reinterpret_cast<const double2*>(w.theta) + (size_t)j * w.theta_stride;
     const double2* V = w.V + (size_t)j * w.nmax * w.vld;
     T* Bl = site_ptr<T>(s, d.b, d.bond);
     const int n = d.n, chi = w.vld;
@@ -1964,7 +1974,7 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
         }
         block_gemm<double2, true, true, 8>(
             d.m, k, n, tm * 64, tn * 64,
-            [&](int r, int q) { return cconv<double2>(th[(size_t)r * n + q]); },
+            [&](int r, int q) { return th[(size_t)r * n + q]; },
             [&](int q, int c) { return V[(size_t)q * chi + c]; },
             [&](int r, int c, double2 v) {
                 const double sc = lam[c] > 0.0 ? 1.0 / (lam[c] * sv) : 0.0;
@@ -1974,7 +1984,7 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     }
     block_gemm<double2, true, true, 8>(
         d.m, k, n, tm * 64, tn * 64,
-        [&](int r, int q) { return cconv<double2>(th[(size_t)r * n + q]); },
+        [&](int r, int q) { return th[(size_t)r * n + q]; },
         [&](int q, int c) { return V[(size_t)q * chi + c]; },
         [&](int r, int c, double2 v) { Bl[(size_t)r * k + c] = cconv<T>(cscale(v, inv)); }, As, Bs);
 }
@@ -2189,6 +2199,22 @@ __global__ void k_reduce_items(DevState s, int nb, int parity, const unsigned ch
 // that runs two chunks on two streams can order the heavy phases of both so that light phases of
 // one chunk share the compute units with a heavy phase of the other.
 // weighted Gram matrix (and, on the QR route, the wide-Theta factorization that replaces it)
+// Theta~ (with the gate unless w.skip_gate) into the workspace, contracted in operand type TC
+template <class T, class TC>
+static void launch_theta(const DevState& s, const DevWork& w, hipStream_t st) {
+    const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
+    if (w.skip_gate) {
+        hipLaunchKernelGGL((k_theta<T, TC>), dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
+        return;
+    }
+    // virtual column tiles: 64/d_r values of c per tile, for the largest d_r
+    const int tv = (s.chi * s.dmax + 63) / 64;
+    if (s.dmax == 2)
+        hipLaunchKernelGGL((k_theta_gate<T, TC, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
+    else
+        hipLaunchKernelGGL((k_theta_gate<T, TC, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
+}
+
 template <class T>
 static void launch_gram(const DevState& s, const DevWork& w, hipStream_t st) {
     if (w.nmax > 64 && w.nmax <= 128) {
@@ -2215,19 +2241,11 @@ static void launch_layer_phase_t(const DevState& s, const DevWork& w, int phase,
     switch (phase) {
     case 0:
         prof_begin(prof, TN_K_THETA, st);
-        if (w.skip_gate) {
-            hipLaunchKernelGGL(k_theta<T>, dim3(tm * tn, w.nitems), dim3(NT), 0, st, s, w, tn);
-        } else {
-            // virtual column tiles: 64/d_r values of c per tile, for the largest d_r
-            const int tv = (s.chi * s.dmax + 63) / 64;
-            if (s.dmax == 2)
-                hipLaunchKernelGGL((k_theta_gate<T, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
-            else
-                hipLaunchKernelGGL((k_theta_gate<T, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
-        }
+        if (w.theta64) launch_theta<T, double2>(s, w, st);
+        else launch_theta<T, T>(s, w, st);
         prof_end(prof, TN_K_THETA, st);
         prof_begin(prof, TN_K_GRAM, st);
-        launch_gram<T>(s, w, st);
+        launch_gram<double2>(s, w, st);
         prof_end(prof, TN_K_GRAM, st);
         return;
     case 1:
@@ -2309,13 +2327,9 @@ void launch_layer_chunk(int prec, const DevState& s, const DevWork& w, hipStream
 
 template <class T>
 static void launch_update_prefix_t(const DevState& s, const DevWork& w, hipStream_t st) {
-    const int tm = (w.mmax + 63) / 64, tn = (w.nmax + 63) / 64;
-    const int tv = (s.chi * s.dmax + 63) / 64;
-    if (s.dmax == 2)
-        hipLaunchKernelGGL((k_theta_gate<T, 4>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
-    else
-        hipLaunchKernelGGL((k_theta_gate<T, 16>), dim3(tm * tv, w.nitems), dim3(NT), 0, st, s, w, tv);
-    launch_gram<T>(s, w, st);
+    if (w.theta64) launch_theta<T, double2>(s, w, st);
+    else launch_theta<T, T>(s, w, st);
+    launch_gram<double2>(s, w, st);
 }
 
 void launch_update_prefix(int prec, const DevState& s, const DevWork& w, hipStream_t st) {

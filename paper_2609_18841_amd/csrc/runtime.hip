@@ -102,6 +102,8 @@ struct tn_state {
     Prof prof3;  // timing of the work launched on mstream
     // this device's address of the static measurement scratch (measure_corr_noalloc)
     char* scratch = nullptr;
+    // split mode: Theta formation on the FP64 matrix cores instead of the FP32 ones
+    int theta64 = 0;
     ~tn_state() {
         for (hipStream_t q : {aux, mstream})
             if (q) {
@@ -185,7 +187,8 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.off_ws = o;
     // update workspace
     size_t u = 0;
-    ly.u_theta = u; u = al(u + (size_t)chunk * mmax * nmax * esz);
+    // Theta~ in complex128 in both precisions
+    ly.u_theta = u; u = al(u + (size_t)chunk * mmax * nmax * 16);
     ly.u_gram = u; u = al(u + (size_t)chunk * nmax * nmax * 16);
     ly.u_refl = u; u = al(u + (size_t)chunk * nmax * nmax * 16);
     ly.u_tau = u; u = al(u + (size_t)chunk * nmax * 16);
@@ -671,6 +674,7 @@ static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, in
     w.mmax = s->mmax;
     w.nmax = s->nmax;
     w.theta_stride = (size_t)s->mmax * s->nmax;
+    w.theta64 = (s->prec == 0 || s->theta64) ? 1 : 0;
     w.theta = ws + s->lay.u_theta;
     w.gram = reinterpret_cast<double2*>(ws + s->lay.u_gram);
     w.refl = reinterpret_cast<double2*>(ws + s->lay.u_refl);
@@ -689,6 +693,7 @@ static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, in
     w.zscratch = reinterpret_cast<double2*>(ws + s->lay.u_z);
     w.pscratch = reinterpret_cast<double2*>(ws + s->lay.u_p);
     w.flags = at<int>(s, s->lay.off_flags);
+    w.counters = at<unsigned long long>(s, s->lay.off_flags + 8);
     w.gsz = reinterpret_cast<int*>(ws + s->lay.u_gsz);
     w.qra = reinterpret_cast<double2*>(ws + s->lay.u_qra);
     w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
@@ -1250,6 +1255,18 @@ extern "C" int tn_overlap(void* h, int on) {
     return TN_OK;
 }
 
+extern "C" int tn_theta_precision(void* h, int bits) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (bits != 32 && bits != 64) return fail(TN_EINVAL, "bits must be 32 or 64");
+    if (s->prec == 0 && bits == 32) return fail(TN_EINVAL, "FP64 mode contracts in FP64 only");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->theta64 = bits == 64 ? 1 : 0;
+    drop_graphs(s);  // captured steps carry the old kernels
+    return TN_OK;
+}
+
 extern "C" int tn_schedule(void* h, int schedule) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     g_err.clear();
@@ -1261,6 +1278,22 @@ extern "C" int tn_schedule(void* h, int schedule) {
 }
 
 // ------------------------------------------------------------------ timing
+extern "C" int tn_stats(void* h, int reset, long long* ql_fallback_items, long long* reorthogonalized_items) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    unsigned long long c[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(c, s->arena + s->lay.off_flags + 8, sizeof c, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (ql_fallback_items) *ql_fallback_items = (long long)c[0];
+    if (reorthogonalized_items) *reorthogonalized_items = (long long)c[1];
+    if (reset) {
+        HIPCHK(hipMemsetAsync(s->arena + s->lay.off_flags + 8, 0, sizeof c, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return TN_OK;
+}
+
 extern "C" int tn_prof_enable(void* h, int on) {
     tn_state* s = reinterpret_cast<tn_state*>(h);
     if (!s) return fail(TN_EINVAL, "null handle");

@@ -81,6 +81,25 @@ def test_path_model_matches_the_stated_flop_model():
     assert m["bound_updates_per_s"] == pytest.approx(1.0 / (m["t_min_us"] * 1e-6))
 
 
+def test_per_bond_work_matches_the_square_model_and_counts_edges():
+    # a saturated bulk bond (64, 64, 64) is the square workload shape of algo_flops / path_model
+    f = bench.item_flops(64, 64, 64, 64)
+    assert f == pytest.approx(bench.algo_flops())
+    assert bench.item_t_min(64, 64, 64, 64) * 1e6 == pytest.approx(bench.path_model(2, 64)["t_min_us"])
+    # L = 8, chi = 4: bonds 0..6 with dims 1 2 4 4 4 4 2 1 -> 7 updates per step, parity 0 first
+    dims = [1, 2, 4, 4, 4, 4, 4, 2, 1]
+    items = bench.layer_items(dims)
+    assert [it[:3] for it in items] == [(1, 2, 4), (4, 4, 4), (4, 4, 4), (4, 2, 1),
+                                        (2, 4, 4), (4, 4, 4), (4, 4, 2)]
+    work, n, tmin = bench.step_work([dims, dims])
+    assert n == 14
+    assert work["hetrd"] == pytest.approx(2 * sum(16.0 / 3.0 * (2 * c) ** 3 for _, _, c, _ in items))
+    assert tmin == pytest.approx(2 * sum(bench.item_t_min(*it) for it in items))
+    # edge bonds are cheaper than bulk ones, so the per-bond count sits below the square count
+    work64, n64, _ = bench.step_work([[1] + [min(64, 2 ** min(b, 64 - b)) for b in range(1, 64)] + [1]])
+    assert n64 == 63 and work64["hetrd"] < 63 * bench.algo_flops()["hetrd"]
+
+
 def test_cpu_baseline_runs_the_oracle_in_processes():
     r = bench.cpu_baseline(8, 8, 0.01, 0.5, procs=2)
     assert r["kind"] == "oracle" and r["cores"] == 2
@@ -113,3 +132,6 @@ def test_oracle_check_reports_each_checkpoint():
         assert spread < 1e-12
     out = bench.oracle_check(tn_inputs, (tensors, lams), L, chi, dt, nz, {5: C[5] + 1e-3 * np.abs(C[5]).max()})
     assert abs(out[5][0] - 1e-3) < 1e-9
+    # a start with a log-norm scales the unnormalized correlations by exp(2 lognorm)
+    out = bench.oracle_check(tn_inputs, (tensors, lams, 0.5 * np.log(2.0)), L, chi, dt, nz, {5: 2.0 * C[5]})
+    assert out[5][0] < 1e-12

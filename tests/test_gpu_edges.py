@@ -147,6 +147,10 @@ def test_exactly_degenerate_spectrum(prec):
     for parity in (0, 1):
         tebd.apply_layer(st, {b: M.gate_heff(mdl, b, 0.0) for b in M.layer_bonds(L, parity)}, parity, chi, cut)
     g.tebd_step(0.0, order=1)
+    # every update of the step holds a tied multiplet: split mode counts each one on the QL route
+    fb, mgs = g.stats(reset=True)
+    assert fb == (3 * (L - 1) if prec == api.SPLIT else 0), fb
+    assert g.stats() == (0, 0)
     C_o, _ = measure.corr_mps(st, normalize=True)
     for inst in range(3):
         t3, l3, ln3, _ = g.get_instance(inst)

@@ -39,8 +39,12 @@ def _normwise(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
-@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
-def test_mps_heff_trotter_matches_oracle(prec, tol):
+# (precision, tolerance, bits of the Theta contraction in split mode)
+PRECS = [(api.FP64, 1e-10, None), (api.SPLIT, 1e-5, 32), (api.SPLIT, 1e-5, 64)]
+
+
+@pytest.mark.parametrize("prec,tol,bits", PRECS)
+def test_mps_heff_trotter_matches_oracle(prec, tol, bits):
     L, chi, dt, nsteps = 8, 16, 0.1, 5
     occ = tn_inputs.neel(L)
     mdl = M.Model(L)
@@ -51,6 +55,8 @@ def test_mps_heff_trotter_matches_oracle(prec, tol):
     C_o, n_o = measure.corr_mps(st, normalize=True)
     g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 2, chi, occ, precision=prec,
                   sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    if bits:
+        g.theta_precision(bits)
     for _ in range(nsteps):
         g.tebd_step(dt, order=1)
     C_g, var, _, nrm = g.measure_corr(normalize=1)
@@ -59,8 +65,8 @@ def test_mps_heff_trotter_matches_oracle(prec, tol):
     g.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
-def test_mpdo_second_order_matches_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,bits", PRECS)
+def test_mpdo_second_order_matches_oracle(prec, tol, bits):
     L, chi, dt, nsteps = 6, 64, 0.05, 6
     occ = tn_inputs.neel(L)
     mdl = M.Model(L)
@@ -71,6 +77,8 @@ def test_mpdo_second_order_matches_oracle(prec, tol):
     C_o, tr_o = measure.corr_mpdo(st)
     g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 1, chi, occ, precision=prec,
                   sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    if bits:
+        g.theta_precision(bits)
     g.tebd_step(dt, order=2, n_steps=nsteps)
     C_g, _, _, tr = g.measure_corr()
     assert _normwise(C_g, C_o) < tol
@@ -268,8 +276,8 @@ def test_state_roundtrip_and_single_layer_on_random_state():
 
 
 @pytest.mark.parametrize("chi", [40, 60])
-@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
-def test_uneven_orders_match_oracle(chi, prec, tol):
+@pytest.mark.parametrize("prec,tol,bits", PRECS)
+def test_uneven_orders_match_oracle(chi, prec, tol, bits):
     """Bond dimensions 40 and 60 at L = 14, so the Hermitian eigenproblems reach orders
     n = 2 chi_r = 80 and 120 next to smaller ones: the two-stage Householder reduction hands
     trailing blocks of order 64 on from orders that are not multiples of 32, and the blocked
@@ -280,6 +288,8 @@ def test_uneven_orders_match_oracle(chi, prec, tol):
     assert max(dims) == chi
     g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 2, chi, tn_inputs.neel(L), precision=prec,
                   sv_cutoff=0.0)
+    if bits:
+        g.theta_precision(bits)
     g.set_instance(0, tensors, lams, 0.0)
     g.replicate(0)
     mdl = M.Model(L)
@@ -301,8 +311,8 @@ def test_uneven_orders_match_oracle(chi, prec, tol):
     g.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
-def test_mpdo_orders_match_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,bits", PRECS)
+def test_mpdo_orders_match_oracle(prec, tol, bits):
     """Local dimension 4 (vectorized density matrix) at chi = 32: the Gram orders n = 4 chi_r reach
     128, so the split path's two-stage Householder reduction, the matrix-core Gram (row weights
     over d_l = 4) and the blocked back-transformation run behind the 16 x 16 Liouvillian gate.
@@ -313,6 +323,8 @@ def test_mpdo_orders_match_oracle(prec, tol):
     assert max(dims) == chi
     g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 2, chi, tn_inputs.neel(L), precision=prec,
                   sv_cutoff=0.0)
+    if bits:
+        g.theta_precision(bits)
     g.set_instance(0, tensors, lams, 0.0)
     g.replicate(0)
     mdl = M.Model(L)

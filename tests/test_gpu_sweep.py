@@ -36,13 +36,14 @@ def _gauge_r_defect(T):
     return np.max(np.abs(M2 - np.eye(T.shape[0])))
 
 
-CASES = [("mps", 1, 8, 32, api.FP64, 1e-10), ("mps", 2, 8, 32, api.FP64, 1e-10),
-         ("mpdo", 2, 6, 64, api.FP64, 1e-10), ("mps", 1, 8, 32, api.SPLIT, 1e-5),
-         ("mpdo", 2, 6, 64, api.SPLIT, 1e-5)]
+CASES = [("mps", 1, 8, 32, api.FP64, 1e-10, None), ("mps", 2, 8, 32, api.FP64, 1e-10, None),
+         ("mpdo", 2, 6, 64, api.FP64, 1e-10, None), ("mps", 1, 8, 32, api.SPLIT, 1e-5, 32),
+         ("mpdo", 2, 6, 64, api.SPLIT, 1e-5, 32), ("mps", 1, 8, 32, api.SPLIT, 1e-5, 64),
+         ("mpdo", 2, 6, 64, api.SPLIT, 1e-5, 64)]
 
 
-@pytest.mark.parametrize("kind,order,L,chi,prec,tol", CASES)
-def test_sweep_matches_oracle(kind, order, L, chi, prec, tol):
+@pytest.mark.parametrize("kind,order,L,chi,prec,tol,bits", CASES)
+def test_sweep_matches_oracle(kind, order, L, chi, prec, tol, bits):
     dt, nsteps = 0.1, 5
     occ = tn_inputs.neel(L)
     ch = M.source_sink_dephasing(L, 0.5, 0.3)
@@ -55,6 +56,8 @@ def test_sweep_matches_oracle(kind, order, L, chi, prec, tol):
     g = api.State(gk, api.Model.channels(L, ch), 2, chi, occ, precision=prec,
                   sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
     g.schedule(api.SCHED_SWEEP)
+    if bits:
+        g.theta_precision(bits)
     g.tebd_step(dt, order=order, n_steps=nsteps)
     if kind == "mpdo":
         C_o, tr_o = measure.corr_mpdo(o)
