@@ -181,6 +181,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the second input's throughput")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run every chunk of a layer on the caller's stream in the timed region")
     ap.add_argument("--overlap-measure", action="store_true",
                     help="measure each output from a snapshot, beside the next interval's steps")
     ap.add_argument("--check-steps", type=int, default=100,
@@ -424,7 +426,6 @@ def _profiled_interval(api, st, noise, inner, dt, B):
         ms, n = st.prof_query(kid)
         kt[name] = {"total_ms": ms, "launches": n, "avg_ms": ms / n if n else 0.0}
     st.prof_enable(False)
-    st.overlap(True)
     return kt, dims
 
 
@@ -502,6 +503,8 @@ def main():
     overlap = args.overlap_measure
     if overlap:
         st.measure_async_enable()
+    if args.no_overlap:
+        st.overlap(False)
 
     def interval(i0, pending):
         # the steps of one output interval, then its measurement: with overlap the measurement of
@@ -607,7 +610,7 @@ def main():
         sst.close()
         del sst
         torch.cuda.empty_cache()
-        return {"value": v, "unit": "two-site updates/s", "steps": n_int, "ql_fallback_items": f,
+        return {"value": v, "unit": "two-site updates/s", "steps": n_int, "cluster_items": f,
                 "reorthogonalized_items": m, "updates": n_int * inner * (L - 1) * B}
 
     # the other Theta precision on the headline input
@@ -679,10 +682,11 @@ def main():
         "config": {"workload": workload, "batch": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner,
                    "input": args.input, "checkpoints": ck_info, "theta_bits": bits,
                    "measurement": "beside the next interval's steps (snapshot)" if overlap else "synchronous",
-                   "timing": "kernel timing off; captured HIP graphs replay the Trotter steps"},
+                   "timing": "kernel timing off; captured HIP graphs replay the Trotter steps",
+                   "chunk_streams": 1 if args.no_overlap else 2},
         "roofline": roof, "path_roofline": path_roof,
         "cpu_baseline": cpu, "plain_fp64": plain, "fp64_batched": fp64b, "secondary_input": second,
-        "eigensolver_routes": {"ql_fallback_items": fb_items, "reorthogonalized_items": mgs_items,
+        "eigensolver_routes": {"cluster_items": fb_items, "reorthogonalized_items": mgs_items,
                                "updates": updates},
         "err_vs_fp64_oracle": err, "oracle_driver_spread": spread, "err_tolerance": ERR_TOLERANCE,
         "err_within_tolerance": None if checks is None else {

@@ -288,13 +288,15 @@ int tn_schedule(void* s, int schedule);
 /* ---- eigensolver path counters ------------------------------------------- */
 
 /* Split precision with n <= 128 and chi <= 64 takes the tridiagonal eigenvectors from bisection
- * and twisted factorization; an item whose kept eigenvalues are closer than 1e-11 lambda_max (a
- * degenerate multiplet) or whose factorization fails goes to the implicit-QL fallback, and an
- * item whose kept eigenvalues are closer than 1e-8 lambda_max has its vectors re-orthogonalized.
- * tn_stats reports how many two-site updates took each route since mps_alloc or the last reset
- * (either output may be NULL); reset = 1 zeroes both counts after reading them.  Other precisions
- * and shapes count nothing.  Returns TN_OK, TN_EINVAL (null handle) or TN_EHIP. */
-int tn_stats(void* s, int reset, long long* ql_fallback_items, long long* reorthogonalized_items);
+ * and twisted factorization.  An item whose kept eigenvalues are closer than 1e-11 lambda_max (a
+ * degenerate multiplet) or whose factorization overflows takes them from inverse iteration
+ * instead (a tridiagonal that is not finite or has no positive eigenvalue from implicit QL);
+ * an item whose kept eigenvalues are closer than 1e-8 lambda_max, and every item of the former
+ * kind, has its vectors re-orthogonalized.  tn_stats reports how many two-site updates took each
+ * route since mps_alloc or the last reset (either output may be NULL); reset = 1 zeroes both
+ * counts after reading them.  Other precisions and shapes count nothing.  Returns TN_OK,
+ * TN_EINVAL (null handle) or TN_EHIP. */
+int tn_stats(void* s, int reset, long long* cluster_items, long long* reorthogonalized_items);
 
 /* ---- kernel timing (HIP events on the library stream) -------------------- */
 #define TN_K_THETA   0  /* Theta formation + gate */

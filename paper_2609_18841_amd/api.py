@@ -267,8 +267,9 @@ class State:
 
     # ---- timing
     def stats(self, reset=False):
-        """(items sent to the implicit-QL fallback, items re-orthogonalized) since mps_alloc or the
-        last reset (split precision, n <= 128, chi <= 64)."""
+        """(items whose vectors came from the degenerate-cluster route (inverse iteration, or QL
+        for a broken tridiagonal), items re-orthogonalized) since mps_alloc or the last reset
+        (split precision, n <= 128, chi <= 64)."""
         a, b = ctypes.c_longlong(), ctypes.c_longlong()
         _check(self.lib.tn_stats(self.h, 1 if reset else 0, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value

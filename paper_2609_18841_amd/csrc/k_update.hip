@@ -1693,11 +1693,15 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
 //             (stationary and progressive LDL^T sweeps, twist where |gamma_r| is smallest), one
 //             modified Gram-Schmidt pass in descending order, then the Householder
 //             back-transformation.
-// Eigenvectors of eigenvalues closer than 1e-11 lambda_max (a degenerate multiplet), or a
-// factorization that overflows, send the item to the logged QL path (k_steqr, k_select,
-// k_vecs_fast run on those items only): fb = 1.  Computed eigenvectors are orthogonal to about
-// eps lambda_max / gap, so the Gram-Schmidt pass runs only when some kept gap is below
-// 1e-8 lambda_max (fb = 2); otherwise fb = 0.  Above that gap the loss of orthogonality stays
+// Kept eigenvalues closer than 1e-11 lambda_max (a degenerate multiplet, where twisted
+// vectors of nearly equal shifts could coincide) take every vector of the item from inverse
+// iteration instead, with shifts kept 10 eps ||T|| apart and distinct pseudo-random starts, so
+// that a cluster's vectors span its invariant subspace; the Gram-Schmidt pass then makes them
+// orthonormal (fb = 3).  A twisted factorization that overflows is redone the same way.  Only
+// a tridiagonal that is not finite or has no positive eigenvalue goes to the logged QL path
+// (k_steqr, k_select, k_vecs_fast run on those items only): fb = 1.  Computed eigenvectors are
+// orthogonal to about eps lambda_max / gap, so the Gram-Schmidt pass runs only when some kept
+// gap is below 1e-8 lambda_max (fb = 2); otherwise fb = 0.  Above that gap the loss of orthogonality stays
 // near 1e-8, below the rounding of the complex64 storage the vectors go to (B_{b+1} = V^+);
 // most bulk bonds of a saturated physical state keep several eigenvalues below 1e-6 lambda_max,
 // so a 1e-6 threshold would send nearly every item through the pass.
@@ -1790,7 +1794,7 @@ __global__ __launch_bounds__(64) void k_bisect(DevState s, DevWork w) {
     const bool tight = lane + 1 < k && !(lam - nxt > TV_TIGHT * lmax);
     const bool close = lane + 1 < k && !(lam - nxt > TV_SEP * lmax);
     const bool bad = !(lmax > 0.0) || !(kept == kept) || !(tr == tr);
-    const int fall = (__any(tight) || bad) ? 1 : (__any(close) ? 2 : 0);
+    const int fall = bad ? 1 : (__any(tight) ? 3 : (__any(close) ? 2 : 0));
     if (lane < k) {
         lam_ptr(s, dm.b, dm.bond)[lane] = lam > 0.0 ? sqrt(lam) / sv : 0.0;
         w.lsel[(size_t)j * w.nmax + lane] = lam;
@@ -1812,6 +1816,79 @@ __device__ __forceinline__ double tv_rcp(double x) {
     return fma(fma(-x, r, 1.0), r, r);
 }
 
+// deterministic start entries in [-1, 1): an integer hash of (column, row)
+__device__ __forceinline__ double tv_start(int c, int i) {
+    unsigned int h = (unsigned int)c * 0x9E3779B1u ^ ((unsigned int)i + 0x7F4A7C15u) * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return (double)h * (2.0 / 4294967296.0) - 1.0;
+}
+
+// Eigenvector column c (lane c of wave 0, c < k) of the tridiagonal T (sd, se) by two steps of
+// inverse iteration, (T - sigma_c I) x' = x, from a pseudo-random start.  The shifts follow the
+// kept eigenvalues in descending order but stay at least 10 eps ||T|| apart: sigma_c =
+// min_{p <= c}(lambda_p + p delta) - c delta.  Each solve factors T - sigma_c I = L D L^T top-down
+// (pivots kept at least eps ||T|| in size, as inverse iteration allows: a shift on an eigenvalue
+// then grows the start by at most 1/(eps ||T||) instead of overflowing; the pivots are kept in the
+// item's rotation-log space) and normalizes the result into column c of zr.
+__device__ void tv_inverse_iteration(const DevWork& w, int j, int n, int k, int c, const double* sd,
+                                     const double* se, double* zr) {
+    const double* lsel = w.lsel + (size_t)j * w.nmax;
+    const double lam = c < k ? lsel[c] : 0.0;
+    double tmax = 0.0;  // max_i |d_i| + |e_{i-1}| + |e_i| >= ||T||
+    for (int i = 0; i < n; ++i) tmax = fmax(tmax, fabs(sd[i]) + fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0));
+    const double delta = 10.0 * DBL_EPSILON * tmax;
+    const double pfloor = fmax(DBL_EPSILON * tmax, DBL_MIN);
+    // prefix minimum over the lanes of lambda_p + p delta
+    double pm = c < k ? lam + c * delta : 1e300;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double v = __shfl_up(pm, o);
+        if (c >= o) pm = fmin(pm, v);
+    }
+    if (c >= k) return;
+    const double sig = pm - c * delta;
+    double* Dp = reinterpret_cast<double*>(w.logcs + (size_t)j * w.logcap) + (size_t)c * n;
+    for (int i = 0; i < n; ++i) zr[i * VF_K + c] = tv_start(c, i);
+    for (int it = 0; it < 2; ++it) {
+        // forward: D_i and z_i = y_i / D_i with y_i = x_i - (e_{i-1} / D_{i-1}) y_{i-1}
+        double dprev = 0.0, yprev = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double dd = sd[i] - sig;
+            double y = zr[i * VF_K + c];
+            if (i > 0) {
+                const double l = se[i - 1] / dprev;
+                dd -= l * se[i - 1];
+                y -= l * yprev;
+            }
+            if (fabs(dd) < pfloor) dd = dd < 0.0 ? -pfloor : pfloor;
+            Dp[i] = dd;
+            zr[i * VF_K + c] = y / dd;
+            dprev = dd;
+            yprev = y;
+        }
+        // backward: x_i = z_i - (e_i / D_i) x_{i+1}, then normalize (by the largest entry first)
+        double x = zr[(n - 1) * VF_K + c], amax = fabs(x);
+        for (int i = n - 2; i >= 0; --i) {
+            x = zr[i * VF_K + c] - (se[i] / Dp[i]) * x;
+            zr[i * VF_K + c] = x;
+            amax = fmax(amax, fabs(x));
+        }
+        const double sc = amax > 0.0 ? 1.0 / amax : 0.0;
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double v = zr[i * VF_K + c] * sc;
+            zr[i * VF_K + c] = v;
+            nrm += v * v;
+        }
+        const double inv = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+        for (int i = 0; i < n; ++i) zr[i * VF_K + c] *= inv;
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
     static_assert((VF_N + 16) * BT_LD * 16 <= VF_N * VF_K * 8, "back-transformation tiles fit in zr");
@@ -1825,8 +1902,7 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
     if (!item_dims(s, w, j, d)) return;
     if (w.fb[j] == 1) return;
     const int n = w.gsz[j], tid = threadIdx.x, k = w.kout[j];
-    const bool mgs = w.fb[j] == 2;
-    if (mgs && tid == 0) atomicAdd(&w.counters[1], 1ull);
+    const bool invit = w.fb[j] == 3;
     const double* gd = w.dd + (size_t)j * w.nmax;
     const double* ge = w.ee + (size_t)j * w.nmax;
     for (int i = tid; i < n; i += NT) {
@@ -1847,7 +1923,7 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
     const double pivmin = DBL_MIN * fmax(1.0, emax2);
     // column c = lane of wave 0: 64 independent recurrences
     const int c = ln;
-    if (wv == 0 && c < k) {
+    if (wv == 0 && c < k && !invit) {
         const double lam = w.lsel[(size_t)j * w.nmax + c];
         // progressive (bottom-up) pivots D-_i of T - lam I, stored in the column
         double dm = sd[n - 1] - lam;
@@ -1906,9 +1982,15 @@ __global__ __launch_bounds__(NT, 2) void k_tvecs(DevState s, DevWork w) {
         for (int i = 0; i < n; ++i) zr[i * VF_K + c] *= inv;
     }
     __syncthreads();
-    if (bad) {
-        if (tid == 0) w.fb[j] = 1;
-        return;
+    const bool redo = invit || bad;  // uniform over the workgroup
+    if (redo) {
+        if (wv == 0) tv_inverse_iteration(w, j, n, k, c, sd, se, zr);
+        __syncthreads();
+    }
+    const bool mgs = redo || w.fb[j] == 2;
+    if (tid == 0) {
+        if (redo) atomicAdd(&w.counters[0], 1ull);
+        if (mgs) atomicAdd(&w.counters[1], 1ull);
     }
     // modified Gram-Schmidt in descending eigenvalue order: column p is final, then removed from p+1..k-1
     const int g = tid >> 6, col = tid & 63;

@@ -2,7 +2,7 @@
 the library accepts (chi = 256, so the Hermitian eigenproblem has n = d chi_r = 512 and takes
 the global-memory Householder / QL / eigenvector kernels), the shortest chain (L = 2, one
 bond), chi = 1 (every update truncates to a product state), exactly tied singular values (the
-rainbow state, which sends split mode to its logged-QL fallback), and independence of an
+rainbow state, which sends split mode to its degenerate-cluster route), and independence of an
 instance's result from the batch it sits in."""
 import numpy as np
 import pytest
@@ -131,8 +131,9 @@ def test_result_does_not_depend_on_the_batch(prec):
 def test_exactly_degenerate_spectrum(prec):
     """The rainbow state (site i shares a particle with site L-1-i) has flat Schmidt spectra; with
     the identity gate (dt = 0) every kept singular value of every bond ties exactly, in complex64
-    too.  Split mode then hands every item to the logged-QL fallback for degenerate multiplets,
-    and FP64 mode meets exact ties in its Jacobi refinement.  Nothing is truncated (rank <= chi),
+    too.  Split mode then takes every item's vectors from inverse iteration with separated shifts
+    and re-orthogonalization (the route for degenerate multiplets), and FP64 mode meets exact
+    ties in its Jacobi refinement.  Nothing is truncated (rank <= chi),
     so bond weights and correlations must match the oracle run on the same input with the same
     truncation (and the state must come back unchanged)."""
     L, chi, cut = 8, 16, 1e-6
@@ -147,9 +148,13 @@ def test_exactly_degenerate_spectrum(prec):
     for parity in (0, 1):
         tebd.apply_layer(st, {b: M.gate_heff(mdl, b, 0.0) for b in M.layer_bonds(L, parity)}, parity, chi, cut)
     g.tebd_step(0.0, order=1)
-    # every update of the step holds a tied multiplet: split mode counts each one on the QL route
+    # the bulk updates hold tied multiplets: split mode counts them on the cluster route, each also
+    # re-orthogonalized; FP64 mode has no such route
     fb, mgs = g.stats(reset=True)
-    assert fb == (3 * (L - 1) if prec == api.SPLIT else 0), fb
+    if prec == api.SPLIT:
+        assert fb >= 3 * (L - 3) and mgs >= fb, (fb, mgs)
+    else:
+        assert (fb, mgs) == (0, 0)
     assert g.stats() == (0, 0)
     C_o, _ = measure.corr_mps(st, normalize=True)
     for inst in range(3):
