@@ -291,8 +291,9 @@ int tn_schedule(void* s, int schedule);
  * and twisted factorization.  An item whose kept eigenvalues are closer than 1e-11 lambda_max (a
  * degenerate multiplet) or whose factorization overflows takes them from inverse iteration
  * instead (a tridiagonal that is not finite or has no positive eigenvalue from implicit QL);
- * an item whose kept eigenvalues are closer than 1e-8 lambda_max, and every item of the former
- * kind, has its vectors re-orthogonalized.  tn_stats reports how many two-site updates took each
+ * an item with two adjacent kept eigenvalues closer than 1.1e-7 sqrt(lambda_p lambda_q) (where
+ * the loss of orthogonality weighted by the two singular values reaches 1e-9), and every item of
+ * the former kind, has its vectors re-orthogonalized.  tn_stats reports how many two-site updates took each
  * route since mps_alloc or the last reset (either output may be NULL); reset = 1 zeroes both
  * counts after reading them.  Other precisions and shapes count nothing.  Returns TN_OK,
  * TN_EINVAL (null handle) or TN_EHIP. */

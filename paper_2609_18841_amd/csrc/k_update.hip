@@ -1699,15 +1699,18 @@ __global__ __launch_bounds__(NT) void k_vecs_fast(DevState s, DevWork w) {
 // that a cluster's vectors span its invariant subspace; the Gram-Schmidt pass then makes them
 // orthonormal (fb = 3).  A twisted factorization that overflows is redone the same way.  Only
 // a tridiagonal that is not finite or has no positive eigenvalue goes to the logged QL path
-// (k_steqr, k_select, k_vecs_fast run on those items only): fb = 1.  Computed eigenvectors are
-// orthogonal to about eps lambda_max / gap, so the Gram-Schmidt pass runs only when some kept
-// gap is below 1e-8 lambda_max (fb = 2); otherwise fb = 0.  Above that gap the loss of orthogonality stays
-// near 1e-8, below the rounding of the complex64 storage the vectors go to (B_{b+1} = V^+);
-// most bulk bonds of a saturated physical state keep several eigenvalues below 1e-6 lambda_max,
-// so a 1e-6 threshold would send nearly every item through the pass.
+// (k_steqr, k_select, k_vecs_fast run on those items only): fb = 1.  Two computed eigenvectors
+// p, q are orthogonal to about eps lambda_max / |lambda_p - lambda_q|, and the state sees that
+// overlap weighted by the singular values of the two directions, sigma_p sigma_q / sigma_0^2 =
+// sqrt(lambda_p lambda_q) / lambda_max (the rows of B_{b+1} = V^+ enter every later contraction
+// with the weights Lambda_b).  The Gram-Schmidt pass therefore runs when some pair of adjacent
+// kept eigenvalues has eps sqrt(lambda_p lambda_q) > 1e-9 |lambda_p - lambda_q| (fb = 2), an
+// effect below 1/50 of the complex64 rounding of the stored tensors otherwise; fb = 0.  Close
+// pairs at the bottom of a physical spectrum (most bulk bonds of a saturated state hold several
+// eigenvalues within 1e-8 lambda_max of each other there) then need no pass.
 #define BS_MAXIT 64
 #define TV_TIGHT 1e-11
-#define TV_SEP 1e-8
+#define TV_ORTH 1e-9
 
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -1792,7 +1795,7 @@ __global__ __launch_bounds__(64) void k_bisect(DevState s, DevWork w) {
     const double sv = kept > 0.0 ? sqrt(kept) : 1.0;
     const double nxt = __shfl_down(lam, 1);
     const bool tight = lane + 1 < k && !(lam - nxt > TV_TIGHT * lmax);
-    const bool close = lane + 1 < k && !(lam - nxt > TV_SEP * lmax);
+    const bool close = lane + 1 < k && !(TV_ORTH * (lam - nxt) >= DBL_EPSILON * sqrt(fmax(lam, 0.0) * fmax(nxt, 0.0)));
     const bool bad = !(lmax > 0.0) || !(kept == kept) || !(tr == tr);
     const int fall = bad ? 1 : (__any(tight) ? 3 : (__any(close) ? 2 : 0));
     if (lane < k) {
