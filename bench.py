@@ -165,6 +165,10 @@ def parse():
     ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--inner", type=int, default=10, help="Trotter steps per output interval")
     ap.add_argument("--dt", type=float, default=0.01)
+    ap.add_argument("--workload", choices=["qsd", "mpdo", "qt", "qsd-wide", "purified"], default="qsd",
+                    help="qsd: the headline (default); the others time the remaining configurations and "
+                         "print their own line (run_workload)")
+    ap.add_argument("--pre", type=int, default=-1, help="untimed steps before timing (other workloads)")
     ap.add_argument("--theta-bits", type=int, choices=[32, 64], default=64,
                     help="matrix cores of the Theta contraction in split mode (the other is timed beside it)")
     ap.add_argument("--input", choices=["physical", "synthetic"], default="physical",
@@ -451,11 +455,143 @@ def roofline_line(api, st, kt, dims, inner, chi):
         work, n_items, tmin
 
 
+def run_workload(args):
+    """Throughput of the configurations besides the headline, from the Neel state, with untimed steps
+    first so that the bond dimensions have grown (and, for trajectories, spread):
+      mpdo      vectorized Lindblad, L = 64, chi = 128 (Theta up to 512 x 512), 2nd order, dt = 0.02:
+                split and FP64, with the split result's distance to the FP64 one on the same steps;
+      qt        1024 quantum trajectories, L = 32, chi = 64, dt = 0.01, jumps from FP64 uniforms
+                (a jumped trajectory skips its Trotter step, so only evolved ones count);
+      qsd-wide  4096 QSD trajectories, L = 64, chi = 32, dt = 0.01, one measurement per 10 steps;
+      purified  locally purified MPS, L = 32, chi = 64, chi_k = 4, dt = 0.02, Kraus step each step.
+    Prints one JSON line."""
+    import torch
+    import tn_inputs
+    from paper_2609_18841_amd import api
+    torch.cuda.set_device(0)
+    wl = args.workload
+    res = {"workload": wl, "unit": "two-site updates/s", "n_gpus": 1, "data": "synthetic", "higher_is_better": True}
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_upd = fn(steps)
+        torch.cuda.synchronize()
+        return n_upd / (time.perf_counter() - t0), n_upd
+
+    if wl == "mpdo":
+        L, chi, dt = 64, 128, 0.02
+        pre = 25 if args.pre < 0 else args.pre
+        out = {}
+        for name, prec in (("split", api.SPLIT), ("fp64", api.FP64)):
+            st = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 1, chi, tn_inputs.neel(L), precision=prec,
+                           sv_cutoff=SV_CUTOFF["split"] if prec == api.SPLIT else SV_CUTOFF["fp64"])
+            if prec == api.SPLIT:
+                st.theta_precision(args.theta_bits)
+            for k in range(pre):
+                st.tebd_step(dt, order=2)
+                if k % 5 == 4:
+                    print(f"# mpdo {name}: untimed step {k + 1}", file=sys.stderr, flush=True)
+
+            def steps(k):
+                for i in range(k):
+                    st.tebd_step(dt, order=2)
+                    print(f"# mpdo {name}: timed step {i + 1}", file=sys.stderr, flush=True)
+                return 94 * k
+            v, n_upd = timed(steps, args.steps)
+            C, _, _, tr = st.measure_corr()
+            out[name] = {"value": v, "updates": n_upd, "C": C, "trace": float(tr[0]),
+                         "max_bond_dim": int(max(st.dims(0)))}
+            st.close()
+            print(f"# mpdo {name}: {v:.1f} updates/s", file=sys.stderr, flush=True)
+        diff = float(np.max(np.abs(out["split"]["C"] - out["fp64"]["C"])) / np.max(np.abs(out["fp64"]["C"])))
+        res.update({"metric": "two-site updates/s, MPDO L=64 chi=128", "value": out["split"]["value"],
+                    "fp64": out["fp64"]["value"], "split_over_fp64": out["split"]["value"] / out["fp64"]["value"],
+                    "split_vs_fp64_C": diff, "trace_split": out["split"]["trace"], "trace_fp64": out["fp64"]["trace"],
+                    "max_bond_dim": out["fp64"]["max_bond_dim"],
+                    "config": {"L": L, "chi": chi, "dt": dt, "order": 2, "untimed_steps": pre, "timed_steps": args.steps,
+                               "start": "Neel", "theta_bits": args.theta_bits}})
+    elif wl == "qt":
+        L, chi, B, dt = 32, 64, 1024, 0.01
+        pre = 100 if args.pre < 0 else args.pre
+        st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
+                       sv_cutoff=SV_CUTOFF["split"])
+        st.theta_precision(args.theta_bits)
+        us = tn_inputs.uniforms(11, (pre + args.steps, B))
+        jumps = [0]
+
+        def qt_steps(k0, k):
+            n_upd = 0
+            for i in range(k0, k0 + k):
+                _, mask = st.apply_jumps(api.MODE_QT, dt, us[i])
+                st.tebd_step(dt, order=1, mask=mask)
+                n_upd += int(B - mask.sum()) * (L - 1)
+                jumps[0] += int(mask.sum())
+            return n_upd
+        qt_steps(0, pre)
+        jumps[0] = 0
+        v, n_upd = timed(lambda k: qt_steps(pre, k), args.steps)
+        mids = np.array([st.dims(b)[L // 2] for b in range(B)])
+        res.update({"metric": "two-site updates/s, QT B=1024 L=32 chi<=64", "value": v, "updates": n_upd,
+                    "jump_fraction": jumps[0] / (B * args.steps),
+                    "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max()), "mean": float(mids.mean())},
+                    "config": {"B": B, "L": L, "chi": chi, "dt": dt, "untimed_steps": pre, "timed_steps": args.steps,
+                               "start": "Neel", "theta_bits": args.theta_bits}})
+        st.close()
+    elif wl == "qsd-wide":
+        L, chi, B, dt, inner = 64, 32, 4096, 0.01, 10
+        pre = 100 if args.pre < 0 else args.pre
+        st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
+                       sv_cutoff=SV_CUTOFF["split"])
+        st.theta_precision(args.theta_bits)
+        nz = tn_inputs.normals(13, (pre + args.steps * inner, B * 4))
+        for k in range(pre):
+            st.tebd_step(dt, order=1)
+            st.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
+
+        def intervals(k):
+            for r in range(k):
+                run_interval(api, st, nz[pre + r * inner:pre + (r + 1) * inner], inner, dt)
+            return k * inner * (L - 1) * B
+        v, n_upd = timed(intervals, args.steps)
+        mids = np.array([st.dims(b)[L // 2] for b in range(0, B, 64)])
+        res.update({"metric": "two-site updates/s, QSD B=4096 L=64 chi<=32", "value": v, "updates": n_upd,
+                    "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max())},
+                    "config": {"B": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner, "untimed_steps": pre,
+                               "timed_intervals": args.steps, "start": "Neel", "theta_bits": args.theta_bits}})
+        st.close()
+    else:
+        L, chi, chik, dt = 32, 64, 4, 0.02
+        pre = 100 if args.pre < 0 else args.pre
+        st = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 1, chi, tn_inputs.neel(L), chi_k_max=chik,
+                       precision=api.SPLIT, sv_cutoff=SV_CUTOFF["split"])
+        st.theta_precision(args.theta_bits)
+
+        def psteps(k):
+            for _ in range(k):
+                st.tebd_step(dt, order=1)
+                st.apply_jumps(api.MODE_KRAUS, dt)
+            return k * (L - 1)
+        psteps(pre)
+        v, n_upd = timed(psteps, args.steps)
+        C, _, _, _ = st.measure_corr()
+        ev = np.linalg.eigvalsh((C + C.conj().T) / 2)
+        res.update({"metric": "two-site updates/s, purified L=32 chi=64 chi_k=4", "value": v, "updates": n_upd,
+                    "eig_C": [float(ev.min()), float(ev.max())], "max_bond_dim": int(max(st.dims(0))),
+                    "config": {"L": L, "chi": chi, "chi_k": chik, "dt": dt, "untimed_steps": pre,
+                               "timed_steps": args.steps, "start": "Neel", "theta_bits": args.theta_bits}})
+        st.close()
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the batch on one GPU is the measured unit)"}))
         sys.exit(2)
+    if args.workload != "qsd":
+        run_workload(args)
+        return
     # the oracle's CPU work runs in processes started before this process touches the GPU: the
     # timing first, then a pool kept for the accuracy checks
     cpu = None if (args.no_cpu or args.calib_copy > 0) else cpu_baseline(args.L, args.chi, args.dt, args.cpu_seconds)

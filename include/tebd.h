@@ -90,7 +90,11 @@ size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int chi_k_max,
 /* Create `batch` instances of the product state init_occ (L ints in {0,1}); all
  * bond dimensions 1.  MPDO: rho = |occ><occ|.  PURIFIED: X = |occ> with a Kraus
  * index of dimension chi_k_max on every jump site (unused columns zero).
- * chi_max >= 1 caps every bond dimension.  sv_cutoff: singular values
+ * chi_max in 1..256 caps every bond dimension.  With D_b the largest bond dimensions the chain
+ * allows under chi_max, every bond's eigenproblem must stay of order <= 512 (split: the Gram
+ * order d_{b+1} D_{b+2}; FP64: min of the two sides of Theta, wide Theta taking the QR route) and
+ * Theta's sides <= 1024; TN_EINVAL otherwise (e.g. MPDO, FP64, L = 8, chi = 256 is accepted: its
+ * Theta reaches 64 x 1024 but its eigenproblems 256).  sv_cutoff: singular values
  * sigma_a <= sv_cutoff * sigma_0 are discarded (Sec. 2.2 truncation).
  * arena: device pointer, arena_bytes >= mps_arena_bytes(...).  hip_stream: a
  * hipStream_t (NULL = default stream).  On success *out is a new handle. */

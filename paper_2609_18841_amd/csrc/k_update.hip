@@ -2110,7 +2110,7 @@ __global__ __launch_bounds__(NT) void k_jac_y(DevState s, DevWork w, int tiles_n
 // weighted cosine exceeds eps*sqrt(m) and both columns are above the rounding floor
 // (eps^2 * sum of all squared norms); the sweeps stop when a sweep rotates nothing.
 __global__ __launch_bounds__(JAC_NT) void k_jacobi(DevState s, DevWork w) {
-    __shared__ double wt[512];
+    __shared__ double wt[1024];  // row weights: m = d_l chi_l <= 1024
     __shared__ double redv[JAC_NT / 64];
     __shared__ int rotated;
     ItemDims d;

@@ -254,7 +254,8 @@ extern "C" size_t mps_arena_bytes(int kind, int L, int batch, int chi_max, int c
     int chunk = chunk_items > 0 ? chunk_items : default_chunk(L, batch, chi_max, dmax);
     int nbm = default_nbm(batch, L, chi_max);
     Layout ly;
-    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, TN_MAX_JUMPS, log_capacity(dmax * chi_max),
+    compute_layout(ly, kind, L, batch, chi_max, dmax, precision, chunk, nbm, TN_MAX_JUMPS,
+                   log_capacity(std::min(dmax * chi_max, 512)),
                    workspace_slots(L, batch, chunk));
     return ly.total;
 }
@@ -364,9 +365,31 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
             delete s;
             return fail(TN_EINVAL, "bond physical dimension d_b*d_{b+1} exceeds 16 (adjacent purified jump sites)");
         }
-    if (chi_max * s->dmax > 512) {
-        delete s;
-        return fail(TN_EINVAL, "chi_max * local dimension must be <= 512");
+    {
+        // Theta of bond b is (d_b D_b) x (d_{b+1} D_{b+2}) with D the largest bond dimensions the
+        // chain allows under chi_max.  The eigenproblem is the Gram matrix of order n = d_{b+1}
+        // D_{b+2} (split mode), or of order min(m, n) in FP64 mode, where wide Theta takes the QR
+        // route; it must stay <= 512, and Theta's sides <= 1024.
+        std::vector<double> D(L + 1, 1.0);
+        double left = 1.0;
+        for (int b = 1; b < L; ++b) {
+            left *= s->dsite[b - 1];
+            double right = 1.0;
+            for (int i = b; i < L && right < 4096.0; ++i) right *= s->dsite[i];
+            D[b] = std::min<double>(chi_max, std::min(left, right));
+        }
+        int worst = 0, side = 0;
+        for (int b = 0; b + 1 < L; ++b) {
+            const int m = (int)(s->dsite[b] * D[b]), n = (int)(s->dsite[b + 1] * D[b + 2]);
+            worst = std::max(worst, precision == 0 ? std::min(m, n) : n);
+            side = std::max(side, std::max(m, n));
+        }
+        if (worst > 512 || side > 1024) {
+            delete s;
+            return fail(TN_EINVAL, precision == 0
+                                       ? "a bond's eigenproblem order min(m, n) would exceed 512 (or a side of Theta 1024)"
+                                       : "a bond's Gram order d chi_r would exceed 512 in split mode");
+        }
     }
     s->site_cap = (size_t)chi_max * s->dmax * chi_max;
     s->esz = precision == 0 ? 16 : 8;
@@ -374,7 +397,7 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
     s->nmax = s->dmax * chi_max;
     s->chunk = default_chunk(L, batch, chi_max, s->dmax);
     s->nbm = default_nbm(batch, L, chi_max);
-    s->logcap = log_capacity(s->nmax);
+    s->logcap = log_capacity(std::min(s->nmax, 512));
     s->gstride = 256;
     s->nbmax = (L - 1 + 1) / 2;
     s->nslots = workspace_slots(L, batch, s->chunk);

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import tn_inputs
-from oracle import model as M, tebd, measure, stochastic, exact
+from oracle import model as M, tebd, measure, stochastic, exact, kraus
 
 pytestmark = pytest.mark.gpu
 
@@ -194,6 +194,89 @@ def test_mpdo_config1_against_oracle_and_exact():
     st.close()
 
 
+def test_mpdo_config1_chi256_is_the_exact_trotter_product():
+    """Configuration 1 without truncation: vectorized Lindblad, L = 8, Neel, J = 1, gamma = 0.5,
+    2nd-order Trotter with dt = 0.05 to t = 2, complex128, chi = 256 (the operator Schmidt rank
+    of the middle cut, so nothing is truncated; Theta reaches 64 x 1024 and 1024 x 64 at the
+    bonds beside the middle).  Every 8 steps the GPU's C and Tr rho are compared with the same
+    gates applied to the dense 4^8 vector of rho and with the oracle's TEBD at chi = 256, to
+    1e-10; at t = 2 the Trotter error against the exact solution is the splitting's own (the
+    dense product is off by 2.0e-4, second order in dt)."""
+    from oracle import tebd as OT, measure as OM, dense, ed
+    L, chi, dt, T = 8, 256, 0.05, 2.0
+    occ = tn_inputs.neel(L)
+    n = int(round(T / dt))
+    st = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 1, chi, occ, precision=api.FP64)
+    mdl = M.Model(L)
+    cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = M.gate_liouville(mdl, b, tau)
+        return cache[(b, tau)]
+    v = dense.product_vector(occ, 4, "mpdo")
+    o = OT.product_state(occ, "mpdo")
+    for blk in range(n // 8):
+        v = dense.trotter_dense(v, fn, 2, dt, 8)
+        for _ in range(8):
+            OT.trotter_step(o, fn, 2, dt, chi, 1e-12)
+        st.tebd_step(dt, order=2, n_steps=8)
+        C, _, _, tr = st.measure_corr()
+        rho = dense.rho_from_vec(v)
+        C_d = ed.corr_from_rho(rho / np.trace(rho), L)
+        C_o, tr_o = OM.corr_mpdo(o)
+        e_d, e_o = _normwise(C, C_d), _normwise(C, C_o)
+        print(f"t={(blk + 1) * 8 * dt:.2f}: GPU vs dense Trotter {e_d:.3e}, vs oracle TEBD {e_o:.3e}, "
+              f"Tr rho - 1 = {tr[0] - 1:.2e}", flush=True)
+        assert e_d < 1e-10 and e_o < 1e-10
+        assert abs(tr[0] - np.trace(rho).real) < 1e-10 and abs(tr[0] - 1.0) < 1e-10
+    d_ex = np.max(np.abs(C - exact.c_exact(T, occ)))
+    assert 1.5e-4 < d_ex < 2.6e-4, d_ex  # second-order splitting error at dt = 0.05
+    st.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(api.FP64, 1e-10), (api.SPLIT, 1e-5)])
+def test_purified_config3_prefix_and_positivity(prec, tol):
+    """Configuration 3: locally purified MPS, L = 32, chi = 64, Kraus dimension chi_k = 4 on the two
+    jump sites (local dimension 8 there, so the edge bonds' Theta is 512 wide), first-order steps
+    of dt = 0.02 each followed by the Kraus compression of eq. MatrixR / eq. NewPurified.  The
+    first 10 steps are compared with the oracle (C and Tr X X^+); the run then continues to
+    t = 5 on the GPU alone, where rho = X X^+ stays a state: eig(C) within [0, 1] and Tr rho
+    finite and positive."""
+    L, chi, chik, dt = 32, 64, 4, 0.02
+    occ = tn_inputs.neel(L)
+    mdl = M.Model(L)
+    dks = [chik if i in (0, L - 1) else 1 for i in range(L)]
+    cache = {}
+
+    def fn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = M.purified_gate(M.gate_heff(mdl, b, tau), dks[b], dks[b + 1])
+        return cache[(b, tau)]
+    o = tebd.product_state(occ, "purified", dk=dks)
+    g = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 1, chi, occ, chi_k_max=chik, precision=prec,
+                  sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
+    for _ in range(10):
+        tebd.trotter_step(o, fn, 1, dt, chi, 1e-12 if prec == api.FP64 else 1e-6)
+        kraus.kraus_step(o, mdl.jumps, dt, chik)
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_KRAUS, dt)
+    C_o, tr_o = measure.corr_mps(o, normalize=True)
+    C_g, _, _, tr = g.measure_corr()
+    assert _normwise(C_g, C_o) < tol
+    assert abs(tr[0] - tr_o) / tr_o < tol
+    for k in range(10, 250):
+        g.tebd_step(dt, order=1)
+        g.apply_jumps(api.MODE_KRAUS, dt)
+    C_g, _, _, tr = g.measure_corr()
+    ev = np.linalg.eigvalsh((C_g + C_g.conj().T) / 2)
+    print(f"purified L=32 t=5: eig(C) in [{ev.min():.2e}, {ev.max():.6f}], "
+          f"max|C - C_exact| = {np.max(np.abs(C_g - exact.c_exact(5.0, occ))):.3e}", flush=True)
+    assert ev.min() > -10 * tol and ev.max() < 1 + 10 * tol
+    assert np.isfinite(tr[0]) and tr[0] > 0
+    g.close()
+
+
 @pytest.mark.parametrize("kind", ["qt", "qsd"])
 def test_trajectory_ensemble_against_exact(kind):
     """Ensembles of seeded trajectories reproduce the Lindblad dynamics within 4 sigma (eq. ErrorCLT)
@@ -220,6 +303,34 @@ def test_trajectory_ensemble_against_exact(kind):
     ne = np.real(np.diag(exact.c_exact(T, occ)))
     assert np.all(np.abs(mean - ne) < 4 * err + 0.01)
     st.close()
+
+
+def test_qsd_config5_batch_against_exact():
+    """Configuration 5 at its shape: 4096 seeded QSD trajectories, L = 64, chi <= 32, complex Gaussian
+    increments, split precision, dt = 0.01, 100 steps (t = 1; the bonds stay below 32 under the
+    split cutoff there).  The batch mean of the linear estimator and its statistical error
+    sqrt(C_var / B) (eq. ErrorCLT, from the library's own batch variance) put the densities and
+    the nearest-neighbour currents within 4 sigma plus the O(dt) splitting bias of the exact
+    solution; the mean norm stays 1 within its own 4 sigma."""
+    L, chi, B, dt, n = 64, 32, 4096, 0.01, 100
+    occ = tn_inputs.neel(L)
+    st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ, precision=api.SPLIT, sv_cutoff=1e-6)
+    nz = tn_inputs.normals(5, (n, B * 4))
+    for k in range(n):
+        st.tebd_step(dt, order=1)
+        st.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
+    C, var, _, nrm = st.measure_corr(normalize=0)
+    st.close()
+    Cx = exact.c_exact(n * dt, occ)
+    sig = np.sqrt(var / B)
+    dens_dev = np.abs(np.real(np.diag(C)) - np.real(np.diag(Cx)))
+    nn_dev = np.abs(np.diag(C, 1) - np.diag(Cx, 1))
+    print(f"QSD B={B} L={L}: max density deviation {dens_dev.max():.3e} (max sigma {np.diag(sig).max():.3e}), "
+          f"max |dC_i,i+1| {nn_dev.max():.3e}", flush=True)
+    assert np.all(dens_dev < 4 * np.diag(sig) + 0.01)
+    assert np.all(nn_dev < 4 * np.diag(sig, 1) + 0.01)
+    assert np.all(np.diag(sig) > 0) and np.diag(sig).max() < 0.02  # 4096 histories
+    assert abs(nrm.mean() - 1) < 4 * nrm.std(ddof=1) / np.sqrt(B) + 0.01
 
 
 def test_mpdo_and_trajectories_agree():
