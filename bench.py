@@ -34,7 +34,7 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "hbm": 8.0e12}
 # rocprofv3 counter summary that holds the HBM bytes per dispatch of each update kernel at this
 # workload's launch shape (8192 / 7936 updates per dispatch); it names the sha256 of the kernel
 # sources it was taken with, and its figures are used only while the sources still match.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_qsd_B256_L64_chi64_split.txt")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_qsd_B1024_L64_chi64_physical_split.txt")
 
 
 def bucket_kernel(bucket, n, chi, hetrd_variant):
@@ -191,6 +191,17 @@ def parse():
                     help="measure each output from a snapshot, beside the next interval's steps")
     ap.add_argument("--check-steps", type=int, default=100,
                     help="Trotter steps of the longer oracle comparison (besides one output interval)")
+    ap.add_argument("--checkpoint-file", default="",
+                    help="npz of the evolved checkpoints: loaded when it exists, else written after evolving")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one stream throughout: warmup intervals, then one profiled interval; prints the "
+                         "roofline line only (for rocprofv3 runs, whose traces then hold one-stream dispatches)")
+    ap.add_argument("--summarize-trace", default="", metavar="DIR",
+                    help="print the per-kernel summary of a rocprofv3 --stats --output-format csv run and exit")
+    ap.add_argument("--summarize-pmc", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="print the per-kernel HBM traffic from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of "
+                         "the workload and of --calib-copy 1024, and exit")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -201,6 +212,69 @@ SV_CUTOFF = {"split": 1e-6, "fp64": 1e-12}
 # the split path's stated bound on correlations against the FP64 oracle, normwise
 # max |dC| / max |C| (the precision pattern's tolerance for FP32 contractions)
 ERR_TOLERANCE = 1e-5
+
+
+def source_hashes():
+    """sha256 prefixes of the kernel sources a profile summary was taken with."""
+    import hashlib
+    out = []
+    for name in ("k_update.hip", "k_measure.hip", "k_jumps.hip", "gemm.h"):
+        path = os.path.join(ROOT, "paper_2609_18841_amd", "csrc", name)
+        out.append(f"{name} sha256:{hashlib.sha256(open(path, 'rb').read()).hexdigest()[:16]}")
+    return ", ".join(out)
+
+
+def _csv_rows(directory, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(path) as f:
+            rows.extend(csv.DictReader(f))
+    return rows
+
+
+def summarize_trace(directory):
+    """Per-kernel table from rocprofv3's kernel_stats.csv: calls, total, average, min, max (ms)."""
+    rows = _csv_rows(directory, "kernel_stats.csv")
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"{'kernel':60s} {'calls':>7s} {'total_ms':>10s} {'avg_ms':>9s} {'min_ms':>9s} {'max_ms':>9s} {'pct':>6s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        n, t = int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6
+        lines.append(f"{r['Name'][:60]:60s} {n:7d} {t:10.3f} {t / n:9.4f} {float(r['MinNs']) / 1e6:9.4f} "
+                     f"{float(r['MaxNs']) / 1e6:9.4f} {100 * t * 1e6 / tot:6.2f}")
+    return lines
+
+
+def _pmc_means(directory, counter):
+    """Mean counter value per dispatch, by kernel, from rocprofv3's counter_collection.csv."""
+    acc = {}
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = r["Kernel_Name"]
+        a = acc.setdefault(k, [0.0, 0])
+        a[0] += float(r["Counter_Value"])
+        a[1] += 1
+    return {k: v / n for k, (v, n) in acc.items()}
+
+
+def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib=1024):
+    """Per-kernel FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and the HBM bytes they stand for, each
+    counter scaled by what it reads for a plain device copy of copy_mib MiB (which reads and writes
+    exactly that many bytes)."""
+    fetch, write = _pmc_means(fetch_dir, "FETCH_SIZE"), _pmc_means(write_dir, "WRITE_SIZE")
+    cf = max(_pmc_means(cfetch_dir, "FETCH_SIZE").values())
+    cw = max(_pmc_means(cwrite_dir, "WRITE_SIZE").values())
+    kib = copy_mib * 1024.0
+    sf, sw = kib / cf, kib / cw
+    lines = [f"# calibration: a {copy_mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB "
+             f"per dispatch -> scale fetch x{sf:.4f}, write x{sw:.4f}",
+             f"{'kernel':60s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'hbm_bytes_scaled':>18s}"]
+    for k in sorted(fetch, key=lambda k: -(fetch[k] * sf + write.get(k, 0.0) * sw)):
+        b = (fetch[k] * sf + write.get(k, 0.0) * sw) * 1024.0
+        lines.append(f"{k[:60]:60s} {fetch[k]:12.1f} {write.get(k, 0.0):12.1f} {b:18.4e}")
+    return lines
 
 
 def evolve_checkpoints(api, tn_inputs, L, chi, n, dt, tmax, seed=4242):
@@ -589,14 +663,21 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU per run: --gpus must be 1 (the batch on one GPU is the measured unit)"}))
         sys.exit(2)
+    if args.summarize_trace:
+        print("\n".join(summarize_trace(args.summarize_trace)))
+        return
+    if args.summarize_pmc:
+        print("\n".join(summarize_pmc(*args.summarize_pmc)))
+        return
     if args.workload != "qsd":
         run_workload(args)
         return
     # the oracle's CPU work runs in processes started before this process touches the GPU: the
     # timing first, then a pool kept for the accuracy checks
-    cpu = None if (args.no_cpu or args.calib_copy > 0) else cpu_baseline(args.L, args.chi, args.dt, args.cpu_seconds)
+    quick = args.calib_copy > 0 or args.profile_only
+    cpu = None if (args.no_cpu or quick) else cpu_baseline(args.L, args.chi, args.dt, args.cpu_seconds)
     pool = None
-    if not args.no_check and args.calib_copy == 0:
+    if not (args.no_check or quick):
         import multiprocessing as mp
         pool = mp.get_context("spawn").Pool(6)
     import torch
@@ -620,9 +701,22 @@ def main():
     log = lambda msg: print(f"# {msg}", file=sys.stderr, flush=True)  # noqa: E731
 
     cks, ck_info = None, None
-    if args.input == "physical" or not args.no_secondary:
+    if args.input == "physical" or not (args.no_secondary or args.profile_only):
         t0 = time.perf_counter()
-        cks, t_ck, ck_dims = evolve_checkpoints(api, tn_inputs, L, chi, args.checkpoints, args.ck_dt, args.ck_tmax)
+        if args.checkpoint_file and os.path.exists(args.checkpoint_file):
+            z = np.load(args.checkpoint_file)
+            cks = [([z[f"t{b}_{i}"] for i in range(L)], [z[f"l{b}_{i}"] for i in range(L - 1)], float(z["ln"][b]))
+                   for b in range(int(z["count"]))]
+            t_ck, ck_dims = float(z["t"]), [list(z["dims"][b]) for b in range(int(z["count"]))]
+        else:
+            cks, t_ck, ck_dims = evolve_checkpoints(api, tn_inputs, L, chi, args.checkpoints, args.ck_dt,
+                                                    args.ck_tmax)
+            if args.checkpoint_file:
+                arrs = {"count": len(cks), "t": t_ck, "dims": np.array(ck_dims), "ln": np.array([c[2] for c in cks])}
+                for b, (tt, ll, _) in enumerate(cks):
+                    arrs.update({f"t{b}_{i}": x for i, x in enumerate(tt)})
+                    arrs.update({f"l{b}_{i}": x for i, x in enumerate(ll)})
+                np.savez(args.checkpoint_file, **arrs)
         ck_info = {"count": args.checkpoints, "evolved_to_t": t_ck, "dt": args.ck_dt, "precision": "fp64",
                    "start": "Neel", "max_bond_dim": int(max(max(d) for d in ck_dims)),
                    "saturated_bonds": int(sum(1 for d in ck_dims[0] if d == chi)),
@@ -639,8 +733,18 @@ def main():
     overlap = args.overlap_measure
     if overlap:
         st.measure_async_enable()
-    if args.no_overlap:
+    if args.no_overlap or args.profile_only:
         st.overlap(False)
+    if args.profile_only:
+        st.tuning(0)  # the autotuner's choice at this shape, without its timing dispatches
+        for w in range(args.warmup):
+            run_interval(api, st, noise[w * inner:(w + 1) * inner], inner, dt)
+        kt, dims0 = _profiled_interval(api, st, noise[args.warmup * inner:], inner, dt, B)
+        roof, work, n_items, tmin = roofline_line(api, st, kt, dims0, inner, chi)
+        print(json.dumps({"profile_only": True, "config": {"batch": B, "L": L, "chi": chi, "input": args.input,
+                                                           "theta_bits": bits, "warmup": args.warmup},
+                          "roofline": roof, "kernel_ms_profiled_interval": kt}))
+        return
 
     def interval(i0, pending):
         # the steps of one output interval, then its measurement: with overlap the measurement of
