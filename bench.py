@@ -187,6 +187,8 @@ def parse():
     ap.add_argument("--no-secondary", action="store_true", help="skip the second input's throughput")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every chunk of a layer on the caller's stream in the timed region")
+    ap.add_argument("--no-buckets", action="store_true",
+                    help="form each layer's chunks from all its bonds in instance order (no bond-size buckets)")
     ap.add_argument("--overlap-measure", action="store_true",
                     help="measure each output from a snapshot, beside the next interval's steps")
     ap.add_argument("--check-steps", type=int, default=100,
@@ -735,6 +737,8 @@ def main():
         st.measure_async_enable()
     if args.no_overlap or args.profile_only:
         st.overlap(False)
+    if args.no_buckets:
+        st.buckets(on=0)
     if args.profile_only:
         st.tuning(0)  # the autotuner's choice at this shape, without its timing dispatches
         for w in range(args.warmup):
@@ -794,6 +798,7 @@ def main():
                  "frac_updates_only": value * t_min_avg / max(1e-9, 1.0 - kt["measure"]["total_ms"] / interval_ms),
                  "measure_share_of_kernel_time": kt["measure"]["total_ms"] / interval_ms,
                  "basis": "value (with the measurement sweep) against the flop model summed over each bond's shape"}
+    buckets = None if args.no_buckets else [[n, nb, hv] for n, nb, hv in st.buckets(parity=0)]
     del st
     torch.cuda.empty_cache()
 
@@ -923,7 +928,8 @@ def main():
                    "input": args.input, "checkpoints": ck_info, "theta_bits": bits,
                    "measurement": "beside the next interval's steps (snapshot)" if overlap else "synchronous",
                    "timing": "kernel timing off; captured HIP graphs replay the Trotter steps",
-                   "chunk_streams": 1 if args.no_overlap else 2},
+                   "chunk_streams": 1 if args.no_overlap else 2,
+                   "bond_size_buckets": buckets},
         "roofline": roof, "path_roofline": path_roof,
         "cpu_baseline": cpu, "plain_fp64": plain, "fp64_batched": fp64b, "secondary_input": second,
         "eigensolver_routes": {"cluster_items": fb_items, "reorthogonalized_items": mgs_items,

@@ -214,7 +214,10 @@ size_t mps_instance_lambda_capacity(const void* s);
 int mps_get_instance(const void* s, int inst, int* dims, double* tensors, double* lambdas,
                      double* lognorm, double* trunc);
 
-/* Overwrite instance `inst` with the same packed layout as mps_get_instance. */
+/* Overwrite instance `inst` with the same packed layout as mps_get_instance.  Each inner bond
+ * dimension dims[b] must lie in 1 .. min(chi_max, d_0 ... d_{b-1}, d_b ... d_{L-1}) (products of
+ * the local dimensions left and right of the bond: the largest Schmidt rank the bond can carry,
+ * which bounds the per-bond workspace); TN_EINVAL otherwise. */
 int mps_set_instance(void* s, int inst, const int* dims, const double* tensors,
                      const double* lambdas, double lognorm);
 
@@ -232,14 +235,30 @@ int tn_gate(int kind, const tn_model* model, int bond, double tau, double* out);
 
 /* For n <= 128 the Householder reduction has two variants (0: FP64 MFMA block columns, run as a
  * head launch down to order 64 and a tail launch for the rest; 1: wave tiles, one launch).  The
- * first tebd_step of a state times both on the Gram matrices of its own first
- * chunk (median of three) when that chunk holds at least 2048 items, and takes the wave-tile
- * kernel only when it is more than 5 % faster; smaller states keep kernel 0 untimed, so the
- * choice does not follow timing noise.  tn_tuning reports the choice
- * (variant_out, may be NULL) and the median times in ms (ms_out[2], may be NULL; zero before
- * tuning or when n > 128); set_variant 0 or 1 overrides the choice, -1 only reports.
- * Returns TN_OK or TN_EINVAL. */
+ * first tebd_step of a state times both, per bucket size class (tn_buckets), on the Gram
+ * matrices of the first chunk of that class (median of three) when that chunk holds at least
+ * 2048 items, and takes the wave-tile kernel for the class only when it is more than 5 % faster;
+ * classes with smaller chunks keep kernel 0 untimed, so the choice does not follow timing noise.
+ * tn_tuning reports the choice of the largest class timed (variant_out, may be NULL) and its
+ * median times in ms (ms_out[2], may be NULL; zero before tuning or when n > 128); set_variant 0
+ * or 1 sets every bucket's choice, -1 only reports.  Returns TN_OK or TN_EINVAL. */
 int tn_tuning(void* s, int set_variant, int* variant_out, float* ms_out);
+
+/* ---- bond-size buckets ------------------------------------------------------ */
+
+/* The items of a layer (Sec. 2.3: every bond of one parity of every instance) are formed into
+ * chunks bucket by bucket: the bond positions of a parity are grouped by the order their Gram
+ * matrix can reach under chi_max (the largest bond dimensions the chain allows): <= 64, <= 128,
+ * <= 256, larger; largest first.  A chunk holds the instances of one bucket's bonds (bond-major),
+ * its per-item workspace strides and its kernel choices follow that bucket's largest shape, and
+ * its Householder kernel is the autotuner's choice for the bucket's size class (timed on the
+ * first chunk of that class, see tn_tuning).  Results do not depend on the bucketing.
+ * on = 1 (the default) buckets, on = 0 forms chunks from all bonds of the layer in instance order
+ * (sized for the state's largest shape), -1 only reports.  count (may be NULL) receives the
+ * number of buckets of the parity (at most 4); nmax, nbonds, hvar (4 ints each, may be NULL)
+ * their largest Gram order, their number of bond positions and their Householder variant.
+ * Returns TN_OK or TN_EINVAL. */
+int tn_buckets(void* s, int on, int parity, int* count, int* nmax, int* nbonds, int* hvar);
 
 /* ---- graph replay --------------------------------------------------------- */
 

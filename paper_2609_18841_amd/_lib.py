@@ -11,7 +11,7 @@ EXPORTS = [
     "mps_last_error", "mps_instance_tensor_capacity", "mps_instance_lambda_capacity",
     "mps_get_instance", "mps_set_instance", "mps_replicate", "tn_gate", "tn_tuning", "tn_graph_enable", "tn_overlap", "tn_schedule", "tn_prof_enable",
     "tn_prof_query", "tn_prof_busy", "tn_measure_async_bytes", "tn_measure_async_enable", "measure_corr_start",
-    "measure_corr_finish", "measure_corr_noalloc", "tn_stats", "tn_theta_precision",
+    "measure_corr_finish", "measure_corr_noalloc", "tn_stats", "tn_theta_precision", "tn_buckets",
 ]
 
 
@@ -59,6 +59,8 @@ def load():
     lib.measure_corr_start.argtypes = [vp, ctypes.c_int]
     lib.measure_corr_finish.restype = ctypes.c_int
     lib.measure_corr_finish.argtypes = [vp, dp, dp, dp, dp]
+    lib.tn_buckets.restype = ctypes.c_int
+    lib.tn_buckets.argtypes = [vp, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip]
     lib.tn_theta_precision.restype = ctypes.c_int
     lib.tn_theta_precision.argtypes = [vp, ctypes.c_int]
     lib.tn_stats.restype = ctypes.c_int

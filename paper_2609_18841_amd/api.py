@@ -292,6 +292,14 @@ class State:
         """Allow (default) or forbid running the chunks of a layer on two streams."""
         _check(self.lib.tn_overlap(self.h, 1 if on else 0))
 
+    def buckets(self, on=-1, parity=0):
+        """[(largest Gram order, bond positions, Householder variant)] of the parity's bond-size
+        buckets; on = 1 / 0 switches bucketing on / off first, -1 only reports."""
+        cnt = ctypes.c_int()
+        nmax, nb, hv = (ctypes.c_int * 4)(), (ctypes.c_int * 4)(), (ctypes.c_int * 4)()
+        _check(self.lib.tn_buckets(self.h, int(on), int(parity), ctypes.byref(cnt), nmax, nb, hv))
+        return [(nmax[i], nb[i], hv[i]) for i in range(cnt.value)]
+
     def theta_precision(self, bits):
         """Split mode: form Theta on the FP32 (32, default) or the FP64 (64) matrix cores."""
         _check(self.lib.tn_theta_precision(self.h, int(bits)))

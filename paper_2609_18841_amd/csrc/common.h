@@ -73,8 +73,10 @@ struct DevState {
 
 // Workspace of one chunk of two-site updates (slot j for the j-th item of the chunk).
 struct DevWork {
-    int item0, nitems;           // first global item index, items in chunk
+    int item0, nitems;           // first item index (within the bucket when bonds != null), items in chunk
     int parity, nb;              // layer parity and bonds per instance in this layer
+    const int* bonds;            // bucket: its bond positions t (bond = parity + 2 t), bond-major items
+    int bsz;                     // instances per bond position in a bucket (the batch)
     const unsigned char* mask;   // B bytes or null
     const double2* gates;        // gate table for this layer: [bond] stride gstride
     int gstride;
@@ -120,9 +122,15 @@ struct DevWork {
 
 // item -> (instance, bond); returns false for masked items
 __device__ __forceinline__ bool item_coords(const DevWork& w, int j, int& b, int& bond) {
-    int g = w.item0 + j;
-    b = g / w.nb;
-    bond = w.parity + 2 * (g % w.nb);
+    const int g = w.item0 + j;
+    if (w.bonds) {
+        // a bucket's items: every instance of its first bond position, then of the next, ...
+        b = g % w.bsz;
+        bond = w.parity + 2 * w.bonds[g / w.bsz];
+    } else {
+        b = g / w.nb;
+        bond = w.parity + 2 * (g % w.nb);
+    }
     if (w.mask && w.mask[b]) return false;
     return true;
 }

@@ -2038,7 +2038,7 @@ __global__ __launch_bounds__(NT) void k_split(DevState s, DevWork w, int tiles_n
     const double sv = w.sout[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s.dims[(size_t)d.b * (s.L + 1) + d.bond + 1] = k;
-        int g = w.item0 + j;
+        const size_t g = (size_t)d.b * w.nb + (d.bond - w.parity) / 2;  // per instance and bond position
         glog[g] = log(sv);
         gwt[g] = w.wout[j];
     }
@@ -2234,7 +2234,7 @@ __global__ __launch_bounds__(NT) void k_jac_store(DevState s, DevWork w, double*
     const double sv = w.sout[j];
     if (tid == 0) {
         s.dims[(size_t)d.b * (s.L + 1) + d.bond + 1] = k;
-        const int g = w.item0 + j;
+        const size_t g = (size_t)d.b * w.nb + (d.bond - w.parity) / 2;  // per instance and bond position
         glog[g] = log(sv);
         gwt[g] = w.wout[j];
     }

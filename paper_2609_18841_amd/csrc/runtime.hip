@@ -52,7 +52,7 @@ void prof_end(Prof* p, int id, hipStream_t st) {
 struct Layout {
     size_t off_tens, off_lam, off_dims, off_lognorm, off_trunc, off_dsite, off_mask, off_jumped, off_glog, off_gwt,
         off_gates, off_rnd, off_vals, off_lval, off_nrm, off_jsite, off_jop, off_jLdL, off_gam, off_ceach, off_cmean, off_cvar,
-        off_flags, off_ws;
+        off_flags, off_bkt, off_ws;
     size_t ws_bytes, total;
     // workspace sub-layout (update)
     size_t u_theta, u_gram, u_refl, u_tau, u_dd, u_ee, u_logi, u_logcs, u_nrot, u_sel, u_kout, u_sout, u_wout, u_V,
@@ -104,6 +104,16 @@ struct tn_state {
     char* scratch = nullptr;
     // split mode: Theta formation on the FP64 matrix cores instead of the FP32 ones
     int theta64 = 0;
+    // bond-size buckets: the bond positions t of each parity grouped by the order their Gram
+    // matrices can reach (structural bond dimensions), largest class first; a chunk holds items
+    // of one bucket, sized and dispatched for that bucket's largest shape, with the Householder
+    // variant the autotuner chose for its class
+    struct Bucket {
+        int start, count, nmax, mmax, hvar;
+        float tune_ms[2];
+    };
+    std::vector<Bucket> bk[2];
+    int bucketing = 1;
     ~tn_state() {
         for (hipStream_t q : {aux, mstream})
             if (q) {
@@ -184,6 +194,7 @@ static void compute_layout(Layout& ly, int kind, int L, int B, int chi, int dmax
     ly.off_cmean = o; o = al(o + (size_t)L * L * 16);
     ly.off_cvar = o; o = al(o + (size_t)L * L * 8);
     ly.off_flags = o; o = al(o + 64);
+    ly.off_bkt = o; o = al(o + (size_t)2 * nbmax * 4);
     ly.off_ws = o;
     // update workspace
     size_t u = 0;
@@ -288,6 +299,51 @@ static size_t packed_tensor_elems(const tn_state* s, const int* dims) {
     return n;
 }
 
+// largest bond dimensions D_0 .. D_L an open chain with local dimensions d allows under chi
+static std::vector<double> structural_dims(const std::vector<int>& d, int chi) {
+    const int L = (int)d.size();
+    std::vector<double> D(L + 1, 1.0);
+    double left = 1.0;
+    for (int b = 1; b < L; ++b) {
+        left *= d[b - 1];
+        double right = 1.0;
+        for (int i = b; i < L && right < 4096.0; ++i) right *= d[i];
+        D[b] = std::min<double>(chi, std::min(left, right));
+    }
+    return D;
+}
+
+// size class of a Gram order: the boundaries at which the update kernels change
+static int size_class(int n) { return n <= 64 ? 0 : (n <= 128 ? 1 : (n <= 256 ? 2 : 3)); }
+
+// the buckets of both parities (host side) and their bond-position table (device side)
+static int build_buckets(tn_state* s) {
+    const std::vector<double> D = structural_dims(s->dsite, s->chi);
+    std::vector<int> table((size_t)2 * s->nbmax, 0);
+    for (int p = 0; p < 2; ++p) {
+        s->bk[p].clear();
+        const int nb = p <= s->L - 2 ? ((s->L - 2 - p) / 2 + 1) : 0;
+        int pos = 0;
+        for (int c = 3; c >= 0; --c) {
+            tn_state::Bucket bkt{pos, 0, 0, 0, s->hvar, {0.0f, 0.0f}};
+            for (int t = 0; t < nb; ++t) {
+                const int bond = p + 2 * t;
+                const int n = (int)(s->dsite[bond + 1] * D[bond + 2]), m = (int)(s->dsite[bond] * D[bond]);
+                if (size_class(n) != c) continue;
+                table[(size_t)p * s->nbmax + pos++] = t;
+                bkt.count++;
+                bkt.nmax = std::max(bkt.nmax, n);
+                bkt.mmax = std::max(bkt.mmax, m);
+            }
+            if (bkt.count) s->bk[p].push_back(bkt);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_bkt, table.data(), table.size() * 4, hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TN_OK;
+}
+
 extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double* tensors, const double* lambdas,
                                 double lognorm);
 extern "C" int mps_replicate(void* h, int src);
@@ -370,14 +426,7 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
         // chain allows under chi_max.  The eigenproblem is the Gram matrix of order n = d_{b+1}
         // D_{b+2} (split mode), or of order min(m, n) in FP64 mode, where wide Theta takes the QR
         // route; it must stay <= 512, and Theta's sides <= 1024.
-        std::vector<double> D(L + 1, 1.0);
-        double left = 1.0;
-        for (int b = 1; b < L; ++b) {
-            left *= s->dsite[b - 1];
-            double right = 1.0;
-            for (int i = b; i < L && right < 4096.0; ++i) right *= s->dsite[i];
-            D[b] = std::min<double>(chi_max, std::min(left, right));
-        }
+        const std::vector<double> D = structural_dims(s->dsite, chi_max);
         int worst = 0, side = 0;
         for (int b = 0; b + 1 < L; ++b) {
             const int m = (int)(s->dsite[b] * D[b]), n = (int)(s->dsite[b + 1] * D[b + 2]);
@@ -434,6 +483,13 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
         }
     }
     s->slot_valid[0] = s->slot_valid[1] = false;
+    {
+        const int rcb = build_buckets(s);
+        if (rcb != TN_OK) {
+            delete s;
+            return rcb;
+        }
+    }
     // constant tables
     int rc;
     {
@@ -522,8 +578,11 @@ extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double
     if (!s || !dims || !tensors || !lambdas) return fail(TN_EINVAL, "null argument");
     if (inst < 0 || inst >= s->B) return fail(TN_EINVAL, "instance out of range");
     if (dims[0] != 1 || dims[s->L] != 1) return fail(TN_EINVAL, "dims[0] and dims[L] must be 1");
+    const std::vector<double> Dmax = structural_dims(s->dsite, s->chi);
     for (int i = 1; i < s->L; ++i)
-        if (dims[i] < 1 || dims[i] > s->chi) return fail(TN_EINVAL, "bond dimension out of range");
+        if (dims[i] < 1 || dims[i] > Dmax[i])
+            return fail(TN_EINVAL, "bond dimension out of range (1 .. min(chi_max, product of the local dimensions "
+                                   "on either side))");
     size_t off = 0;
     for (int i = 0; i < s->L; ++i) {
         size_t ne = (size_t)dims[i] * s->dsite[i] * dims[i + 1];
@@ -684,19 +743,23 @@ static int check_flags(tn_state* s) {
 // ------------------------------------------------------------------ TEBD
 // workspace view of the chunk of items [i0, i0 + nitems) of one layer
 static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, int nitems,
-                          const unsigned char* mask_dev, int wslot = 0) {
+                          const unsigned char* mask_dev, int wslot = 0, const tn_state::Bucket* bkt = nullptr) {
     char* ws = s->arena + s->lay.off_ws + (size_t)wslot * s->lay.u_bytes;
     DevWork w;
     w.item0 = (int)i0;
     w.nitems = nitems;
     w.parity = parity;
     w.nb = nb;
+    w.bonds = bkt ? at<int>(s, s->lay.off_bkt) + (size_t)parity * s->nbmax + bkt->start : nullptr;
+    w.bsz = s->B;
     w.mask = mask_dev;
     w.gates = reinterpret_cast<const double2*>(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16);
     w.gstride = s->gstride;
-    w.mmax = s->mmax;
-    w.nmax = s->nmax;
-    w.theta_stride = (size_t)s->mmax * s->nmax;
+    // per-item strides and kernel choices follow the bucket's largest shape (the workspace is sized
+    // for the state's, which bounds every bucket's)
+    w.mmax = bkt ? bkt->mmax : s->mmax;
+    w.nmax = bkt ? bkt->nmax : s->nmax;
+    w.theta_stride = (size_t)w.mmax * w.nmax;
     w.theta64 = (s->prec == 0 || s->theta64) ? 1 : 0;
     w.theta = ws + s->lay.u_theta;
     w.gram = reinterpret_cast<double2*>(ws + s->lay.u_gram);
@@ -722,14 +785,16 @@ static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, in
     w.qtau = reinterpret_cast<double2*>(ws + s->lay.u_qtau);
     w.qr_route = s->prec == 0 ? 1 : 0;
     w.jacobi = s->prec == 0 ? 1 : 0;
-    w.vld = s->prec == 0 ? s->nmax : s->chi;
-    w.Y = w.gram;  // the Gram slot is free once the Householder reduction has read it
-    w.ldy = s->nmax;
-    w.ysz = (size_t)s->nmax * s->nmax;
+    w.vld = s->prec == 0 ? w.nmax : s->chi;
+    // Y = Theta~ V (m x r, r <= n) goes into the Gram slot, which is free once the Householder
+    // reduction has read it; a bucket's items can have m > n, so its rows take max(m, n)
+    w.Y = w.gram;
+    w.ldy = std::max(w.mmax, w.nmax);
+    w.ysz = (size_t)w.ldy * w.nmax;
     w.lsel = reinterpret_cast<double*>(ws + s->lay.u_lsel);
     // split mode with n <= 128 and chi <= 64 takes the bisection path (kernels in k_update.hip)
-    w.fb = (s->prec == 1 && s->nmax <= 128 && s->chi <= 64) ? reinterpret_cast<int*>(ws + s->lay.u_fb) : nullptr;
-    w.hvar = s->hvar;
+    w.fb = (s->prec == 1 && w.nmax <= 128 && s->chi <= 64) ? reinterpret_cast<int*>(ws + s->lay.u_fb) : nullptr;
+    w.hvar = bkt ? bkt->hvar : s->hvar;
     return w;
 }
 
@@ -751,12 +816,25 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
         HIPCHK(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
     }
     int c = 0;
-    for (long i0 = 0; i0 < total; i0 += s->chunk, ++c) {
-        const int nitems = (int)std::min((long)s->chunk, total - i0);
-        const int ws = two ? (c & 1) : 0;
-        DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws);
-        launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
-        HIPCHK(hipGetLastError());
+    if (s->bucketing) {
+        for (const tn_state::Bucket& bkt : s->bk[parity]) {
+            const long items = (long)s->B * bkt.count;
+            for (long i0 = 0; i0 < items; i0 += s->chunk, ++c) {
+                const int nitems = (int)std::min((long)s->chunk, items - i0);
+                const int ws = two ? (c & 1) : 0;
+                DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws, &bkt);
+                launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
+                HIPCHK(hipGetLastError());
+            }
+        }
+    } else {
+        for (long i0 = 0; i0 < total; i0 += s->chunk, ++c) {
+            const int nitems = (int)std::min((long)s->chunk, total - i0);
+            const int ws = two ? (c & 1) : 0;
+            DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws);
+            launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
+            HIPCHK(hipGetLastError());
+        }
     }
     if (two) {
         HIPCHK(hipEventRecord(s->ev_join, s->aux));
@@ -834,35 +912,69 @@ static int run_step(tn_state* s, const std::vector<std::pair<int, int>>& layers,
 static int autotune(tn_state* s, int slot) {
     if (s->tuned) return TN_OK;
     s->tuned = 1;
-    if (s->nmax > 128) return TN_OK;
     const int nb = (s->L - 2) / 2 + 1;  // parity 0 bonds
-    const long total = (long)s->B * nb;
-    const int nitems = (int)std::min((long)s->chunk, total);
-    if (nitems < TUNE_MIN_ITEMS) return TN_OK;
-    DevState ds = dev_state(s);
-    DevWork w = chunk_work(s, 0, nb, slot, 0, nitems, nullptr);
-    launch_update_prefix(s->prec, ds, w, s->stream);
-    HIPCHK(hipGetLastError());
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    float med[2];
-    for (int v = 0; v < 2; ++v) {
-        float t[3];
-        for (int rep = 0; rep < 3; ++rep) {
-            HIPCHK(hipEventRecord(e0, s->stream));
-            launch_hetrd_variant(ds, w, v, s->stream);
-            HIPCHK(hipEventRecord(e1, s->stream));
-            HIPCHK(hipEventSynchronize(e1));
-            HIPCHK(hipEventElapsedTime(&t[rep], e0, e1));
-        }
-        std::sort(t, t + 3);
-        med[v] = t[1];
-        s->tune_ms[v] = t[1];
+    // what is timed: the first chunk of each size class of the parity-0 buckets (the parity-1
+    // buckets of a class take the same choice), or the first chunk of the layer when bucketing is
+    // off; only orders <= 128 have two Householder variants
+    std::vector<std::pair<int, const tn_state::Bucket*>> cand;
+    if (s->bucketing) {
+        for (const tn_state::Bucket& bkt : s->bk[0])
+            if (bkt.nmax <= 128) cand.push_back({size_class(bkt.nmax), &bkt});
+    } else if (s->nmax <= 128) {
+        cand.push_back({size_class(s->nmax), nullptr});
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    s->hvar = med[1] < TUNE_MARGIN * med[0] ? 1 : 0;
+    int choice[4] = {-1, -1, -1, -1};
+    float tms[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    if (!cand.empty()) {
+        DevState ds = dev_state(s);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (const auto& c : cand) {
+            const int cls = c.first;
+            const long items = (long)s->B * (c.second ? c.second->count : nb);
+            const int nitems = (int)std::min((long)s->chunk, items);
+            if (nitems < TUNE_MIN_ITEMS || choice[cls] >= 0) continue;
+            DevWork w = chunk_work(s, 0, nb, slot, 0, nitems, nullptr, 0, c.second);
+            launch_update_prefix(s->prec, ds, w, s->stream);
+            HIPCHK(hipGetLastError());
+            for (int v = 0; v < 2; ++v) {
+                float t[3];
+                for (int rep = 0; rep < 3; ++rep) {
+                    HIPCHK(hipEventRecord(e0, s->stream));
+                    launch_hetrd_variant(ds, w, v, s->stream);
+                    HIPCHK(hipEventRecord(e1, s->stream));
+                    HIPCHK(hipEventSynchronize(e1));
+                    HIPCHK(hipEventElapsedTime(&t[rep], e0, e1));
+                }
+                std::sort(t, t + 3);
+                tms[cls][v] = t[1];
+            }
+            choice[cls] = tms[cls][1] < TUNE_MARGIN * tms[cls][0] ? 1 : 0;
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    for (int p = 0; p < 2; ++p)
+        for (tn_state::Bucket& bkt : s->bk[p]) {
+            const int cls = size_class(bkt.nmax);
+            if (choice[cls] >= 0) {
+                bkt.hvar = choice[cls];
+                bkt.tune_ms[0] = tms[cls][0];
+                bkt.tune_ms[1] = tms[cls][1];
+            }
+        }
+    // the state-wide variant (unbucketed layers, sweeps) is the choice of the largest class timed
+    for (int cls = 3; cls >= 0; --cls)
+        if (choice[cls] >= 0) {
+            s->hvar = choice[cls];
+            s->tune_ms[0] = tms[cls][0];
+            s->tune_ms[1] = tms[cls][1];
+            if (!s->bucketing)
+                for (int p = 0; p < 2; ++p)
+                    for (tn_state::Bucket& bkt : s->bk[p]) bkt.hvar = choice[cls];
+            break;
+        }
     return TN_OK;
 }
 
@@ -1247,6 +1359,8 @@ extern "C" int tn_tuning(void* h, int set_variant, int* variant_out, float* ms_o
     if (set_variant >= 0) {
         hipStreamSynchronize(s->stream);
         s->hvar = set_variant;
+        for (int p = 0; p < 2; ++p)
+            for (tn_state::Bucket& bkt : s->bk[p]) bkt.hvar = set_variant;
         s->tuned = 1;
         drop_graphs(s);  // captured launches carry the old variant
     }
@@ -1287,6 +1401,26 @@ extern "C" int tn_theta_precision(void* h, int bits) {
     HIPCHK(hipStreamSynchronize(s->stream));
     s->theta64 = bits == 64 ? 1 : 0;
     drop_graphs(s);  // captured steps carry the old kernels
+    return TN_OK;
+}
+
+extern "C" int tn_buckets(void* h, int on, int parity, int* count, int* nmax, int* nbonds, int* hvar) {
+    tn_state* s = reinterpret_cast<tn_state*>(h);
+    g_err.clear();
+    if (!s) return fail(TN_EINVAL, "null handle");
+    if (on < -1 || on > 1 || parity < 0 || parity > 1) return fail(TN_EINVAL, "on must be -1, 0 or 1, parity 0 or 1");
+    if (on >= 0) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        s->bucketing = on;
+        drop_graphs(s);  // captured steps carry the old chunking
+    }
+    const std::vector<tn_state::Bucket>& bk = s->bk[parity];
+    if (count) *count = (int)bk.size();
+    for (size_t i = 0; i < bk.size() && i < 4; ++i) {
+        if (nmax) nmax[i] = bk[i].nmax;
+        if (nbonds) nbonds[i] = bk[i].count;
+        if (hvar) hvar[i] = bk[i].hvar;
+    }
     return TN_OK;
 }
 
