@@ -564,6 +564,8 @@ def run_workload(args):
                            sv_cutoff=SV_CUTOFF["split"] if prec == api.SPLIT else SV_CUTOFF["fp64"])
             if prec == api.SPLIT:
                 st.theta_precision(args.theta_bits)
+            if args.no_buckets:
+                st.buckets(on=0)
             for k in range(pre):
                 st.tebd_step(dt, order=2)
                 if k % 5 == 4:
@@ -586,13 +588,15 @@ def run_workload(args):
                     "split_vs_fp64_C": diff, "trace_split": out["split"]["trace"], "trace_fp64": out["fp64"]["trace"],
                     "max_bond_dim": out["fp64"]["max_bond_dim"],
                     "config": {"L": L, "chi": chi, "dt": dt, "order": 2, "untimed_steps": pre, "timed_steps": args.steps,
-                               "start": "Neel", "theta_bits": args.theta_bits}})
+                               "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
     elif wl == "qt":
         L, chi, B, dt = 32, 64, 1024, 0.01
         pre = 100 if args.pre < 0 else args.pre
         st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
                        sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
+        if args.no_buckets:
+            st.buckets(on=0)
         us = tn_inputs.uniforms(11, (pre + args.steps, B))
         jumps = [0]
 
@@ -612,7 +616,7 @@ def run_workload(args):
                     "jump_fraction": jumps[0] / (B * args.steps),
                     "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max()), "mean": float(mids.mean())},
                     "config": {"B": B, "L": L, "chi": chi, "dt": dt, "untimed_steps": pre, "timed_steps": args.steps,
-                               "start": "Neel", "theta_bits": args.theta_bits}})
+                               "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
         st.close()
     elif wl == "qsd-wide":
         L, chi, B, dt, inner = 64, 32, 4096, 0.01, 10
@@ -620,6 +624,8 @@ def run_workload(args):
         st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
                        sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
+        if args.no_buckets:
+            st.buckets(on=0)
         nz = tn_inputs.normals(13, (pre + args.steps * inner, B * 4))
         for k in range(pre):
             st.tebd_step(dt, order=1)
@@ -634,7 +640,7 @@ def run_workload(args):
         res.update({"metric": "two-site updates/s, QSD B=4096 L=64 chi<=32", "value": v, "updates": n_upd,
                     "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max())},
                     "config": {"B": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner, "untimed_steps": pre,
-                               "timed_intervals": args.steps, "start": "Neel", "theta_bits": args.theta_bits}})
+                               "timed_intervals": args.steps, "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
         st.close()
     else:
         L, chi, chik, dt = 32, 64, 4, 0.02
@@ -642,6 +648,8 @@ def run_workload(args):
         st = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 1, chi, tn_inputs.neel(L), chi_k_max=chik,
                        precision=api.SPLIT, sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
+        if args.no_buckets:
+            st.buckets(on=0)
 
         def psteps(k):
             for _ in range(k):
@@ -655,7 +663,7 @@ def run_workload(args):
         res.update({"metric": "two-site updates/s, purified L=32 chi=64 chi_k=4", "value": v, "updates": n_upd,
                     "eig_C": [float(ev.min()), float(ev.max())], "max_bond_dim": int(max(st.dims(0))),
                     "config": {"L": L, "chi": chi, "chi_k": chik, "dt": dt, "untimed_steps": pre,
-                               "timed_steps": args.steps, "start": "Neel", "theta_bits": args.theta_bits}})
+                               "timed_steps": args.steps, "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
         st.close()
     print(json.dumps(res))
 
