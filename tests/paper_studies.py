@@ -2,6 +2,8 @@
 
 Not a pytest module (the short trend checks live in test_gpu_studies.py); each run takes minutes:
     python tests/paper_studies.py mpdo      # Sec. 3.1, fig-Algo1a/b: chi 64 (dt 0.01, 0.003), chi 32 (dt 0.01)
+    python tests/paper_studies.py mpdo --only 64,0.001 --stop-at 9.5 --save a.npz   # dt 0.001, in two
+    python tests/paper_studies.py mpdo --only 64,0.001 --resume a.npz               # sittings
     python tests/paper_studies.py purified  # Sec. 3.2, fig-Algo2a/b: chi 64, chi_k 4, dt 0.003
     python tests/paper_studies.py qt        # Sec. 4.1, fig-Algo3a/b and fig-Algo5: 3000 histories, chi 16
     python tests/paper_studies.py qsd       # Sec. 4.2, fig-Algo4a/b and fig-Algo5: 3000 histories, chi 16
@@ -50,21 +52,40 @@ def log(msg):
     print(msg, flush=True)
 
 
-def run_mpdo(api):
+def run_mpdo(api, only=None, stop_at=None, resume=None, save=None):
+    """only: one (chi, dt) instead of the three runs; stop_at: end the run at the first output time
+    >= stop_at and write the state and the rows so far to `save` (an npz), from which `resume`
+    continues (runs longer than one sitting split in two)."""
     out = []
-    for chi, dt in ((64, 0.01), (64, 0.003), (32, 0.01)):
+    for chi, dt in ([only] if only else ((64, 0.01), (64, 0.003), (32, 0.01))):
         st = api.State(api.KIND_MPDO, api.Model.free_fermion(N, J, GAMMA), 1, chi, OCC, precision=api.SPLIT,
                        sv_cutoff=1e-6)
         st.theta_precision(64)
         n, every = schedule(dt)
-        rows, t0 = [], time.time()
-        for k in range(1, n + 1):
+        rows, t0, k0 = [], time.time(), 0
+        if resume:
+            z = np.load(resume)
+            k0 = int(z["k"])
+            st.set_instance(0, [z[f"t{i}"] for i in range(N)], [z[f"l{i}"] for i in range(N - 1)], float(z["ln"]))
+            rows = json.loads(str(z["rows"]))
+            log(f"mpdo chi={chi} dt={dt}: resumed at step {k0} (t = {k0 * dt:.2f})")
+        for k in range(k0 + 1, n + 1):
             st.tebd_step(dt, order=2)
             if k % every == 0 or k == n:
                 C, _, _, tr = st.measure_corr()
                 e_n, e_j = rms(C, exact.c_exact(k * dt, OCC, J, GAMMA))
                 rows.append({"t": k * dt, "rms_n": e_n, "rms_j": e_j, "trace": float(tr[0])})
                 log(f"mpdo chi={chi} dt={dt} t={k * dt:.2f}: rms n {e_n:.3e} j {e_j:.3e} ({time.time() - t0:.0f} s)")
+                if stop_at is not None and k * dt >= stop_at and k < n:
+                    tens, lams, ln, _ = st.get_instance(0)
+                    arrs = {"k": k, "ln": ln, "rows": json.dumps(rows)}
+                    arrs.update({f"t{i}": x for i, x in enumerate(tens)})
+                    arrs.update({f"l{i}": x for i, x in enumerate(lams)})
+                    np.savez(save, **arrs)
+                    log(f"mpdo chi={chi} dt={dt}: stopped at step {k}, state in {save}")
+                    st.close()
+                    return [{"chi": chi, "dt": dt, "order": 2, "precision": "split (Theta FP64)", "rows": rows,
+                             "stopped_at_step": k}]
         out.append({"chi": chi, "dt": dt, "order": 2, "precision": "split (Theta FP64)", "rows": rows})
         st.close()
     return out
@@ -145,12 +166,20 @@ def main():
     ap.add_argument("study", choices=["mpdo", "purified", "qt", "qsd"])
     ap.add_argument("--out", default="")
     ap.add_argument("--noise", choices=["gauss", "binary"], default="gauss", help="QSD increments")
+    ap.add_argument("--only", default="", help="mpdo: one run, 'chi,dt'")
+    ap.add_argument("--stop-at", type=float, default=None, help="mpdo: stop at this time and save the state")
+    ap.add_argument("--save", default="", help="mpdo: npz written at --stop-at")
+    ap.add_argument("--resume", default="", help="mpdo: npz to continue from")
     args = ap.parse_args()
     import torch
     from paper_2609_18841_amd import api
     torch.cuda.set_device(0)
-    res = {"mpdo": run_mpdo, "purified": run_purified}.get(
-        args.study, lambda a: run_trajectories(a, args.study, args.noise))(api)
+    only = None
+    if args.only:
+        c, d = args.only.split(",")
+        only = (int(c), float(d))
+    res = {"mpdo": lambda a: run_mpdo(a, only, args.stop_at, args.resume or None, args.save or None),
+           "purified": run_purified}.get(args.study, lambda a: run_trajectories(a, args.study, args.noise))(api)
     doc = {"study": args.study, "N": N, "J": J, "gamma": GAMMA, "start": "vacuum", "results": res}
     if args.out:
         with open(args.out, "w") as f:
