@@ -815,26 +815,29 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
         HIPCHK(hipEventRecord(s->ev_fork, s->stream));
         HIPCHK(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
     }
+    // a bucket's items (or the layer's) go out in the fewest chunks of at most s->chunk, of equal
+    // size, so that the two streams get equal shares
     int c = 0;
-    if (s->bucketing) {
-        for (const tn_state::Bucket& bkt : s->bk[parity]) {
-            const long items = (long)s->B * bkt.count;
-            for (long i0 = 0; i0 < items; i0 += s->chunk, ++c) {
-                const int nitems = (int)std::min((long)s->chunk, items - i0);
-                const int ws = two ? (c & 1) : 0;
-                DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws, &bkt);
-                launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
-                HIPCHK(hipGetLastError());
-            }
-        }
-    } else {
-        for (long i0 = 0; i0 < total; i0 += s->chunk, ++c) {
-            const int nitems = (int)std::min((long)s->chunk, total - i0);
+    auto chunks = [&](long items, const tn_state::Bucket* bkt) -> int {
+        const long nch = (items + s->chunk - 1) / s->chunk;
+        const long per = (items + nch - 1) / nch;
+        for (long i0 = 0; i0 < items; i0 += per, ++c) {
+            const int nitems = (int)std::min(per, items - i0);
             const int ws = two ? (c & 1) : 0;
-            DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws);
+            DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws, bkt);
             launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
             HIPCHK(hipGetLastError());
         }
+        return TN_OK;
+    };
+    if (s->bucketing) {
+        for (const tn_state::Bucket& bkt : s->bk[parity]) {
+            const int rc = chunks((long)s->B * bkt.count, &bkt);
+            if (rc != TN_OK) return rc;
+        }
+    } else {
+        const int rc = chunks(total, nullptr);
+        if (rc != TN_OK) return rc;
     }
     if (two) {
         HIPCHK(hipEventRecord(s->ev_join, s->aux));
