@@ -127,9 +127,11 @@ def step_work(all_dims):
 
 
 def profiled_traffic(kernel):
-    """HBM bytes per launch of the timing bucket whose kernel is `kernel` (the sum over its template
-    instances: the Householder reduction is a head and a tail dispatch) from the committed counter
-    summary, or None when the summary is missing or was taken with different kernel sources."""
+    """HBM bytes per launch of the timing bucket whose kernel is `kernel`, from the committed counter
+    summary, or None when the summary is missing or was taken with different kernel sources.  A
+    launch may be several dispatches (the Householder reduction of a chunk is a head and a tail, and
+    chunks of order <= 64 have the tail only), so the bytes of every template instance are weighted
+    by its dispatch count and divided by the largest count, which is the number of launches."""
     import hashlib
     try:
         lines = open(TRAFFIC_PROFILE).read().splitlines()
@@ -143,16 +145,17 @@ def profiled_traffic(kernel):
         path = os.path.join(ROOT, "paper_2609_18841_amd", "csrc", name)
         if hashlib.sha256(open(path, "rb").read()).hexdigest()[:16] != h:
             return None
-    tot, found = 0.0, False
+    tot, launches = 0.0, 0
     for ln in lines:
         if ln.startswith("#"):
             continue
         parts = ln.split()
-        nm = " ".join(parts[:-3]).replace("void ", "").split("<")[0].strip()
+        nm = " ".join(parts[:-4]).replace("void ", "").split("<")[0].strip()
         if nm == kernel:
-            tot += float(parts[-1])
-            found = True
-    return tot if found else None
+            n = int(parts[-4])
+            tot += float(parts[-1]) * n
+            launches = max(launches, n)
+    return tot / launches if launches else None
 
 
 def parse():
@@ -248,8 +251,9 @@ def summarize_trace(directory):
     return lines
 
 
-def _pmc_means(directory, counter):
-    """Mean counter value per dispatch, by kernel, from rocprofv3's counter_collection.csv."""
+def _pmc_means(directory, counter, counts=False):
+    """Mean counter value per dispatch, by kernel, from rocprofv3's counter_collection.csv (and, with
+    counts, the number of dispatches of each kernel)."""
     acc = {}
     for r in _csv_rows(directory, "counter_collection.csv"):
         if r.get("Counter_Name") != counter:
@@ -258,24 +262,25 @@ def _pmc_means(directory, counter):
         a = acc.setdefault(k, [0.0, 0])
         a[0] += float(r["Counter_Value"])
         a[1] += 1
-    return {k: v / n for k, (v, n) in acc.items()}
+    means = {k: v / n for k, (v, n) in acc.items()}
+    return (means, {k: n for k, (_, n) in acc.items()}) if counts else means
 
 
 def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib=1024):
     """Per-kernel FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and the HBM bytes they stand for, each
     counter scaled by what it reads for a plain device copy of copy_mib MiB (which reads and writes
     exactly that many bytes)."""
-    fetch, write = _pmc_means(fetch_dir, "FETCH_SIZE"), _pmc_means(write_dir, "WRITE_SIZE")
+    (fetch, ndisp), write = _pmc_means(fetch_dir, "FETCH_SIZE", counts=True), _pmc_means(write_dir, "WRITE_SIZE")
     cf = max(_pmc_means(cfetch_dir, "FETCH_SIZE").values())
     cw = max(_pmc_means(cwrite_dir, "WRITE_SIZE").values())
     kib = copy_mib * 1024.0
     sf, sw = kib / cf, kib / cw
     lines = [f"# calibration: a {copy_mib} MiB device copy reads FETCH_SIZE {cf:.1f} KiB and WRITE_SIZE {cw:.1f} KiB "
              f"per dispatch -> scale fetch x{sf:.4f}, write x{sw:.4f}",
-             f"{'kernel':60s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'hbm_bytes_scaled':>18s}"]
+             f"{'kernel':60s} {'dispatches':>10s} {'FETCH_KiB':>12s} {'WRITE_KiB':>12s} {'hbm_bytes_scaled':>18s}"]
     for k in sorted(fetch, key=lambda k: -(fetch[k] * sf + write.get(k, 0.0) * sw)):
         b = (fetch[k] * sf + write.get(k, 0.0) * sw) * 1024.0
-        lines.append(f"{k[:60]:60s} {fetch[k]:12.1f} {write.get(k, 0.0):12.1f} {b:18.4e}")
+        lines.append(f"{k[:60]:60s} {ndisp[k]:10d} {fetch[k]:12.1f} {write.get(k, 0.0):12.1f} {b:18.4e}")
     return lines
 
 

@@ -48,7 +48,7 @@ def _rows(path):
         if ln.startswith("#") or ln.startswith("kernel ") or not ln.strip():
             continue
         parts = ln.split()
-        out[" ".join(parts[:-3])] = float(parts[-1])
+        out[" ".join(parts[:-4])] = (int(parts[-4]), float(parts[-1]))
     return out
 
 
@@ -61,7 +61,10 @@ def test_profiled_traffic_sums_a_buckets_dispatches(tmp_path, monkeypatch):
     if got is None:
         pytest.skip("committed summary was taken with other kernel sources")
     assert len(hetrd) == 2  # head and tail
-    assert got == pytest.approx(sum(hetrd))
+    # bytes weighted by dispatches, per launch (every chunk has a tail; chunks of order <= 64 no head)
+    launches = max(n for n, _ in hetrd)
+    assert got == pytest.approx(sum(n * b for n, b in hetrd) / launches)
+    assert got <= sum(b for _, b in hetrd)
     assert bench.profiled_traffic("no_such_kernel") is None
     # a summary whose source hash differs is not used
     fake = tmp_path / "traffic.txt"
