@@ -294,7 +294,8 @@ class State:
 
     def buckets(self, on=-1, parity=0):
         """[(largest Gram order, bond positions, Householder variant)] of the parity's bond-size
-        buckets; on = 1 / 0 switches bucketing on / off first, -1 only reports."""
+        buckets; on = 1 (layers of more than one chunk), 2 (every layer) or 0 (off) switches the
+        bucketing first, -1 only reports."""
         cnt = ctypes.c_int()
         nmax, nb, hv = (ctypes.c_int * 4)(), (ctypes.c_int * 4)(), (ctypes.c_int * 4)()
         _check(self.lib.tn_buckets(self.h, int(on), int(parity), ctypes.byref(cnt), nmax, nb, hv))

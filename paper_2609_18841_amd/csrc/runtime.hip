@@ -805,32 +805,45 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
     const long total = (long)s->B * nb;
     double* glog = at<double>(s, s->lay.off_glog);
     double* gwt = at<double>(s, s->lay.off_gwt);
-    // Items of one layer are independent.  With two workspace slots, odd chunks run on aux with
-    // their own slot, forked after the work already on the main stream and joined back before the
-    // layer's reduction.  (Ordering the heavy phases of the two streams into one chain, so that
-    // light phases of one chunk run beside heavy phases of the other, measured no faster than
-    // this plain alternation: the kernels share the compute units' LDS bandwidth.)
-    const bool two = s->nslots == 2 && s->overlap && s->aux && total > s->chunk;
+    // Items of one layer are independent.  With two workspace slots, chunks run on the main
+    // stream or on aux (with aux's own slot), forked after the work already on the main stream and
+    // joined back before the layer's reduction.  (Ordering the heavy phases of the two streams
+    // into one chain, so that light phases of one chunk run beside heavy phases of the other,
+    // measured no faster than plain alternation: the kernels share the compute units' LDS
+    // bandwidth.)
+    // Buckets (bucketing 1) when the layer spans more than one chunk; a layer that fits one chunk
+    // goes out whole, since one launch sequence beats several small ones in a row.  Bucketing 2
+    // buckets every layer.
+    const bool bucketed = s->bucketing == 2 || (s->bucketing == 1 && total > s->chunk);
+    long nch = 0;
+    if (bucketed)
+        for (const tn_state::Bucket& bkt : s->bk[parity]) nch += ((long)s->B * bkt.count + s->chunk - 1) / s->chunk;
+    else
+        nch = (total + s->chunk - 1) / s->chunk;
+    const bool two = s->nslots == 2 && s->overlap && s->aux && nch > 1;
     if (two) {
         HIPCHK(hipEventRecord(s->ev_fork, s->stream));
         HIPCHK(hipStreamWaitEvent(s->aux, s->ev_fork, 0));
     }
     // a bucket's items (or the layer's) go out in the fewest chunks of at most s->chunk, of equal
-    // size, so that the two streams get equal shares
-    int c = 0;
+    // size; each chunk goes to the stream with less work queued so far, work counted as
+    // items x order^3 (the Householder reduction's share)
+    double load[2] = {0.0, 0.0};
     auto chunks = [&](long items, const tn_state::Bucket* bkt) -> int {
-        const long nch = (items + s->chunk - 1) / s->chunk;
-        const long per = (items + nch - 1) / nch;
-        for (long i0 = 0; i0 < items; i0 += per, ++c) {
+        const long nc = (items + s->chunk - 1) / s->chunk;
+        const long per = (items + nc - 1) / nc;
+        const double ord = bkt ? bkt->nmax : s->nmax;
+        for (long i0 = 0; i0 < items; i0 += per) {
             const int nitems = (int)std::min(per, items - i0);
-            const int ws = two ? (c & 1) : 0;
+            const int ws = two ? (load[1] < load[0] ? 1 : 0) : 0;
+            load[ws] += (double)nitems * ord * ord * ord;
             DevWork w = chunk_work(s, parity, nb, slot, i0, nitems, mask_dev, ws, bkt);
             launch_layer_chunk(s->prec, ds, w, ws ? s->aux : s->stream, ws ? &s->prof2 : &s->prof, glog, gwt);
             HIPCHK(hipGetLastError());
         }
         return TN_OK;
     };
-    if (s->bucketing) {
+    if (bucketed) {
         for (const tn_state::Bucket& bkt : s->bk[parity]) {
             const int rc = chunks((long)s->B * bkt.count, &bkt);
             if (rc != TN_OK) return rc;
@@ -1411,7 +1424,7 @@ extern "C" int tn_buckets(void* h, int on, int parity, int* count, int* nmax, in
     tn_state* s = reinterpret_cast<tn_state*>(h);
     g_err.clear();
     if (!s) return fail(TN_EINVAL, "null handle");
-    if (on < -1 || on > 1 || parity < 0 || parity > 1) return fail(TN_EINVAL, "on must be -1, 0 or 1, parity 0 or 1");
+    if (on < -1 || on > 2 || parity < 0 || parity > 1) return fail(TN_EINVAL, "on must be -1, 0, 1 or 2, parity 0 or 1");
     if (on >= 0) {
         HIPCHK(hipStreamSynchronize(s->stream));
         s->bucketing = on;

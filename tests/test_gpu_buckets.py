@@ -44,6 +44,30 @@ def test_bucket_table_follows_the_structural_dims(kind, L, chi):
     st.close()
 
 
+def test_small_layers_go_out_whole_unless_forced():
+    """Default bucketing leaves a layer that fits one chunk whole; on = 2 buckets it.  Both give the
+    unbucketed result up to rounding (this checks the switch, the next test the results)."""
+    L, chi = 16, 64
+    out = []
+    for on in (1, 2, 0):
+        st = api.State(api.KIND_MPS, api.Model.free_fermion(L), 3, chi, [0] * L, precision=api.FP64)
+        st.tuning(set_variant=0)
+        st.buckets(on=on)
+        for b in range(3):
+            t, lam, _ = tn_inputs.random_isometric_mps(40 + b, L, chi)
+            st.set_instance(b, t, lam, 0.0)
+        st.tebd_step(0.05, order=2, n_steps=2)
+        out.append([st.get_instance(b) for b in range(3)])
+        st.close()
+    # on = 1 with a one-chunk layer is the unbucketed launch: bit for bit
+    for a, b in zip(out[0], out[2]):
+        for ta, tb in zip(a[0], b[0]):
+            assert np.array_equal(ta, tb)
+    for a, b in zip(out[1], out[2]):
+        for la, lb in zip(a[1], b[1]):
+            assert np.max(np.abs(la - lb)) < 1e-12
+
+
 def test_autotuner_times_each_size_class():
     """L = 64, chi = 64, B = 1024: the middle bonds (order 128) and the edge bonds (order <= 64)
     form two classes whose first chunks are both large enough to time."""
@@ -72,7 +96,7 @@ def _run(kind, prec, L, chi, B, on, nsteps, seed):
     st = api.State(kind, api.Model.free_fermion(L), B, chi, [0] * L, precision=prec,
                    sv_cutoff=1e-12 if prec == api.FP64 else 1e-6)
     st.tuning(set_variant=0)
-    st.buckets(on=on)
+    st.buckets(on=on)  # 2: bucket these one-chunk layers too
     for b in range(B):
         t, lam, _ = tn_inputs.random_isometric_mps(seed + b, L, chi, d=d)
         st.set_instance(b, t, lam, 0.0)
@@ -87,14 +111,14 @@ def _run(kind, prec, L, chi, B, on, nsteps, seed):
                                                  (api.KIND_MPS, api.FP64, 16, 64, 1e-12),
                                                  (api.KIND_MPDO, api.SPLIT, 8, 32, 2e-6)])
 def test_results_do_not_depend_on_the_bucketing(kind, prec, L, chi, tol):
-    """Mixed bucket sizes (orders 8 .. 128).  With the bucketing on, a small bond's workspace
+    """Mixed bucket sizes (orders 8 .. 128), every layer bucketed.  With the bucketing on, a small bond's workspace
     strides and kernel tiles follow its bucket instead of the largest bond, which changes the
     order of some roundings (and with it the gauge of nearly sign-free eigenvector columns), not
     the result: Schmidt values, bond dimensions, log-norms and correlation matrices agree to
     rounding.  Tolerances: 1e-12 in FP64; in split precision a few units of complex64 storage
     rounding (6e-8) times the 3 x 2 layers and the chain's accumulation."""
     B = 5
-    on, C_on, n_on = _run(kind, prec, L, chi, B, 1, 3, 300)
+    on, C_on, n_on = _run(kind, prec, L, chi, B, 2, 3, 300)
     off, C_off, n_off = _run(kind, prec, L, chi, B, 0, 3, 300)
     for a, b in zip(on, off):
         assert len(a[1]) == len(b[1])
@@ -113,6 +137,7 @@ def test_bucketed_mpdo_across_the_order_128_boundary_matches_oracle():
     occ = [1, 0, 1, 0, 0, 1]
     mdl = M.Model(L)
     g = api.State(api.KIND_MPDO, api.Model.free_fermion(L), 1, chi, occ, precision=api.SPLIT, sv_cutoff=1e-6)
+    g.buckets(on=2)  # one instance: every layer fits one chunk
     assert [n for n, _, _ in g.buckets(parity=0)] == [64]
     assert [n for n, _, _ in g.buckets(parity=1)] == [256, 16]
     st = tebd.product_state(occ, "mpdo")
