@@ -64,6 +64,9 @@ struct Layout {
 struct tn_state {
     int kind, L, B, chi, chik, prec, dmax, njump;
     int chunk, nbm, mmax, nmax, logcap, gstride, nbmax;
+    // largest m = d_b D_b and Gram order n = d_{b+1} D_{b+2} over all bonds, D the largest bond
+    // dimensions the chain allows (mmax, nmax: the workspace bounds d_max chi)
+    int mstruct = 1, nstruct = 1;
     double cutoff;
     std::vector<int> dsite;
     TnModelHost model;
@@ -334,6 +337,8 @@ static int build_buckets(tn_state* s) {
                 bkt.count++;
                 bkt.nmax = std::max(bkt.nmax, n);
                 bkt.mmax = std::max(bkt.mmax, m);
+                s->nstruct = std::max(s->nstruct, n);
+                s->mstruct = std::max(s->mstruct, m);
             }
             if (bkt.count) s->bk[p].push_back(bkt);
         }
@@ -755,10 +760,10 @@ static DevWork chunk_work(tn_state* s, int parity, int nb, int slot, long i0, in
     w.mask = mask_dev;
     w.gates = reinterpret_cast<const double2*>(s->arena + s->lay.off_gates + (size_t)slot * (s->L - 1) * 256 * 16);
     w.gstride = s->gstride;
-    // per-item strides and kernel choices follow the bucket's largest shape (the workspace is sized
-    // for the state's, which bounds every bucket's)
-    w.mmax = bkt ? bkt->mmax : s->mmax;
-    w.nmax = bkt ? bkt->nmax : s->nmax;
+    // per-item strides and kernel choices follow the bucket's largest shape, or without a bucket the
+    // largest over the chain (the workspace is sized for d_max chi, which bounds both)
+    w.mmax = bkt ? bkt->mmax : s->mstruct;
+    w.nmax = bkt ? bkt->nmax : s->nstruct;
     w.theta_stride = (size_t)w.mmax * w.nmax;
     w.theta64 = (s->prec == 0 || s->theta64) ? 1 : 0;
     w.theta = ws + s->lay.u_theta;
@@ -832,7 +837,7 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
     auto chunks = [&](long items, const tn_state::Bucket* bkt) -> int {
         const long nc = (items + s->chunk - 1) / s->chunk;
         const long per = (items + nc - 1) / nc;
-        const double ord = bkt ? bkt->nmax : s->nmax;
+        const double ord = bkt ? bkt->nmax : s->nstruct;
         for (long i0 = 0; i0 < items; i0 += per) {
             const int nitems = (int)std::min(per, items - i0);
             const int ws = two ? (load[1] < load[0] ? 1 : 0) : 0;
@@ -936,8 +941,8 @@ static int autotune(tn_state* s, int slot) {
     if (s->bucketing) {
         for (const tn_state::Bucket& bkt : s->bk[0])
             if (bkt.nmax <= 128) cand.push_back({size_class(bkt.nmax), &bkt});
-    } else if (s->nmax <= 128) {
-        cand.push_back({size_class(s->nmax), nullptr});
+    } else if (s->nstruct <= 128) {
+        cand.push_back({size_class(s->nstruct), nullptr});
     }
     int choice[4] = {-1, -1, -1, -1};
     float tms[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
