@@ -253,9 +253,9 @@ int tn_tuning(void* s, int set_variant, int* variant_out, float* ms_out);
  * its per-item workspace strides and its kernel choices follow that bucket's largest shape, and
  * its Householder kernel is the autotuner's choice for the bucket's size class (timed on the
  * first chunk of that class, see tn_tuning).  Results do not depend on the bucketing beyond the
- * order of roundings.  on = 1 (the default) buckets the layers whose items span more than one
- * chunk and sends a layer that fits one chunk out whole (one launch sequence instead of several
- * small ones in a row); on = 2 buckets every layer; on = 0 forms chunks from all bonds of the layer
+ * order of roundings.  on = 1 (the default) buckets the layers with at least as many items as the
+ * device has compute units and sends a smaller layer out whole (it is latency-bound: one launch
+ * sequence instead of several in a row); on = 2 buckets every layer; on = 0 forms chunks from all bonds of the layer
  * in instance order (sized for the state's largest shape); -1 only reports.  Chunks go to the
  * library's two streams by the work already queued on each (items x order^3).  count (may be NULL) receives the
  * number of buckets of the parity (at most 4); nmax, nbonds, hvar (4 ints each, may be NULL)

@@ -294,7 +294,7 @@ class State:
 
     def buckets(self, on=-1, parity=0):
         """[(largest Gram order, bond positions, Householder variant)] of the parity's bond-size
-        buckets; on = 1 (layers of more than one chunk), 2 (every layer) or 0 (off) switches the
+        buckets; on = 1 (layers of at least one item per compute unit), 2 (every layer) or 0 (off) switches the
         bucketing first, -1 only reports."""
         cnt = ctypes.c_int()
         nmax, nb, hv = (ctypes.c_int * 4)(), (ctypes.c_int * 4)(), (ctypes.c_int * 4)()

@@ -117,6 +117,7 @@ struct tn_state {
     };
     std::vector<Bucket> bk[2];
     int bucketing = 1;
+    int ncu = 256;  // compute units of the arena's device: the smallest layer that is bucketed
     ~tn_state() {
         for (hipStream_t q : {aux, mstream})
             if (q) {
@@ -477,6 +478,9 @@ extern "C" int mps_alloc(void** out, int kind, const tn_model* model, int batch,
             delete s;
             return rc0;
         }
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            s->ncu = ncu;
     }
     if (s->nslots == 2) {
         bool ok = hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking) == hipSuccess;
@@ -816,10 +820,10 @@ static int run_layer(tn_state* s, int parity, int slot, const unsigned char* mas
     // into one chain, so that light phases of one chunk run beside heavy phases of the other,
     // measured no faster than plain alternation: the kernels share the compute units' LDS
     // bandwidth.)
-    // Buckets (bucketing 1) when the layer spans more than one chunk; a layer that fits one chunk
-    // goes out whole, since one launch sequence beats several small ones in a row.  Bucketing 2
-    // buckets every layer.
-    const bool bucketed = s->bucketing == 2 || (s->bucketing == 1 && total > s->chunk);
+    // Buckets (bucketing 1) when the layer has at least one item per compute unit; a smaller layer
+    // is latency-bound and goes out whole, since one launch sequence then beats several in a row.
+    // Bucketing 2 buckets every layer.
+    const bool bucketed = s->bucketing == 2 || (s->bucketing == 1 && total >= s->ncu);
     long nch = 0;
     if (bucketed)
         for (const tn_state::Bucket& bkt : s->bk[parity]) nch += ((long)s->B * bkt.count + s->chunk - 1) / s->chunk;

@@ -45,8 +45,9 @@ def test_bucket_table_follows_the_structural_dims(kind, L, chi):
 
 
 def test_small_layers_go_out_whole_unless_forced():
-    """Default bucketing leaves a layer that fits one chunk whole; on = 2 buckets it.  Both give the
-    unbucketed result up to rounding (this checks the switch, the next test the results)."""
+    """Default bucketing leaves a layer of fewer items than compute units whole; on = 2 buckets it.
+    Both give the unbucketed result up to rounding (this checks the switch, the next test the
+    results)."""
     L, chi = 16, 64
     out = []
     for on in (1, 2, 0):
@@ -59,7 +60,7 @@ def test_small_layers_go_out_whole_unless_forced():
         st.tebd_step(0.05, order=2, n_steps=2)
         out.append([st.get_instance(b) for b in range(3)])
         st.close()
-    # on = 1 with a one-chunk layer is the unbucketed launch: bit for bit
+    # on = 1 with a 24-item layer is the unbucketed launch: bit for bit
     for a, b in zip(out[0], out[2]):
         for ta, tb in zip(a[0], b[0]):
             assert np.array_equal(ta, tb)
