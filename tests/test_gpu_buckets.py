@@ -110,9 +110,11 @@ def _run(kind, prec, L, chi, B, on, nsteps, seed):
 
 @pytest.mark.parametrize("kind,prec,L,chi,tol", [(api.KIND_MPS, api.SPLIT, 16, 64, 2e-6),
                                                  (api.KIND_MPS, api.FP64, 16, 64, 1e-12),
-                                                 (api.KIND_MPDO, api.SPLIT, 8, 32, 2e-6)])
+                                                 (api.KIND_MPDO, api.SPLIT, 8, 32, 2e-6),
+                                                 (api.KIND_MPDO, api.FP64, 6, 64, 1e-12)])
 def test_results_do_not_depend_on_the_bucketing(kind, prec, L, chi, tol):
-    """Mixed bucket sizes (orders 8 .. 128), every layer bucketed.  With the bucketing on, a small bond's workspace
+    """Mixed bucket sizes (orders 4 .. 256; the FP64 MPDO chain puts its order-256 bond through
+    the general eigen path and Jacobi refinement), every layer bucketed.  With the bucketing on, a small bond's workspace
     strides and kernel tiles follow its bucket instead of the largest bond, which changes the
     order of some roundings (and with it the gauge of nearly sign-free eigenvector columns), not
     the result: Schmidt values, bond dimensions, log-norms and correlation matrices agree to
