@@ -80,6 +80,8 @@ typedef struct tn_model {
     const double* jump_op;    /* n_jumps * 4 complex: 2x2 [out, in] local operator (no string) */
     const double* gamma;      /* n_jumps rates >= 0 */
 } tn_model;
+/* mps_alloc refuses (TN_EINVAL) a model whose h_bond, jump_op or gamma holds a value that is not
+ * finite. */
 
 /* Bytes of device arena needed for a state of the given shape plus the
  * workspace of one chunk of chunk_items two-site updates (chunk_items <= 0:
@@ -133,7 +135,9 @@ int tebd_step(void* s, double dt, int order, int n_steps, const unsigned char* m
  *   h^eff Trotter step under mask_out, as for TN_MODE_QT).
  * TN_MODE_QSD_SHIFT (MPS): per channel in channel order,
  *   psi <- (1 + dW_k sqrt(gamma_k)(L_k - l_k)) (1 + dt gamma_k (conj(l_k) L_k - |l_k|^2/2)) psi;
- *   same rnd layout as TN_MODE_QSD. */
+ *   same rnd layout as TN_MODE_QSD.
+ * TN_EINVAL (before anything runs) when dt is negative or not finite, a uniform of rnd lies
+ * outside [0, 1] or a normal is not finite. */
 int apply_jumps(void* s, int mode, double dt, const double* rnd, int noise_kind,
                 int* jumped_out, unsigned char* mask_out);
 
@@ -217,7 +221,8 @@ int mps_get_instance(const void* s, int inst, int* dims, double* tensors, double
 /* Overwrite instance `inst` with the same packed layout as mps_get_instance.  Each inner bond
  * dimension dims[b] must lie in 1 .. min(chi_max, d_0 ... d_{b-1}, d_b ... d_{L-1}) (products of
  * the local dimensions left and right of the bond: the largest Schmidt rank the bond can carry,
- * which bounds the per-bond workspace); TN_EINVAL otherwise. */
+ * which bounds the per-bond workspace); TN_EINVAL otherwise, and also when a tensor entry or the
+ * lognorm is not finite or a bond weight is negative or not finite. */
 int mps_set_instance(void* s, int inst, const int* dims, const double* tensors,
                      const double* lambdas, double lognorm);
 

@@ -13,6 +13,7 @@ KIND_MPS, KIND_MPDO, KIND_PURIFIED = 0, 1, 2
 FP64, SPLIT = 0, 1
 MODE_QT, MODE_QSD, MODE_KRAUS, MODE_QT_SHIFT, MODE_QSD_SHIFT = 0, 1, 2, 3, 4
 NOISE_GAUSS, NOISE_BINARY = 0, 1
+TN_OK, TN_EINVAL, TN_ENOMEM, TN_EHIP, TN_ENOCONV, TN_ENUMERIC = 0, -1, -2, -3, -4, -5
 SCHED_LAYER, SCHED_SWEEP = 0, 1
 K_THETA, K_GRAM, K_HETRD, K_STEQR, K_VECS, K_SPLIT, K_MEASURE, K_JUMPS = range(8)
 K_NAMES = ["theta", "gram", "hetrd", "steqr", "vecs", "split", "measure", "jumps"]

@@ -256,8 +256,12 @@ static bool model_ok(const tn_model* m, std::string& why) {
     if (m->n_jumps > 0 && (!m->jump_site || !m->jump_op || !m->gamma)) { why = "jump arrays are null"; return false; }
     for (int q = 0; q < m->n_jumps; ++q) {
         if (m->jump_site[q] < 0 || m->jump_site[q] >= m->L) { why = "jump site out of range"; return false; }
-        if (!(m->gamma[q] >= 0)) { why = "negative rate"; return false; }
+        if (!(m->gamma[q] >= 0) || !std::isfinite(m->gamma[q])) { why = "rate negative or not finite"; return false; }
+        for (int e = 0; e < 8; ++e)
+            if (!std::isfinite(m->jump_op[8 * q + e])) { why = "jump operator not finite"; return false; }
     }
+    for (size_t e = 0; e < (size_t)(m->L - 1) * 32; ++e)
+        if (!std::isfinite(m->h_bond[e])) { why = "h_bond not finite"; return false; }
     return true;
 }
 
@@ -592,6 +596,17 @@ extern "C" int mps_set_instance(void* h, int inst, const int* dims, const double
         if (dims[i] < 1 || dims[i] > Dmax[i])
             return fail(TN_EINVAL, "bond dimension out of range (1 .. min(chi_max, product of the local dimensions "
                                    "on either side))");
+    {
+        size_t nt = 0, nl = 0;
+        for (int i = 0; i < s->L; ++i) nt += (size_t)dims[i] * s->dsite[i] * dims[i + 1];
+        for (int b = 1; b < s->L; ++b) nl += dims[b];
+        for (size_t e = 0; e < 2 * nt; ++e)
+            if (!std::isfinite(tensors[e])) return fail(TN_EINVAL, "tensor entries must be finite");
+        for (size_t e = 0; e < nl; ++e)
+            if (!(lambdas[e] >= 0.0) || !std::isfinite(lambdas[e]))
+                return fail(TN_EINVAL, "bond weights must be finite and >= 0");
+        if (!std::isfinite(lognorm)) return fail(TN_EINVAL, "lognorm must be finite");
+    }
     size_t off = 0;
     for (int i = 0; i < s->L; ++i) {
         size_t ne = (size_t)dims[i] * s->dsite[i] * dims[i + 1];
@@ -1312,6 +1327,15 @@ extern "C" int apply_jumps(void* h, int mode, double dt, const double* rnd, int 
     if (qsd && noise_kind != 0 && noise_kind != 1) return fail(TN_EINVAL, "unknown noise kind");
     if (mode == TN_MODE_KRAUS && s->kind != TN_KIND_PURIFIED)
         return fail(TN_EINVAL, "Kraus compression needs kind PURIFIED");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(TN_EINVAL, "dt must be finite and >= 0");
+    if (qt || qsd) {
+        // uniforms (QT draws, binary increments) in [0, 1]; Gaussian increments finite
+        const bool unif = qt || noise_kind == 1;
+        const size_t n = qt ? (size_t)s->B : (size_t)s->B * s->njump * (noise_kind == 0 ? 2 : 1);
+        for (size_t e = 0; e < n; ++e)
+            if (!std::isfinite(rnd[e]) || (unif && !(rnd[e] >= 0.0 && rnd[e] <= 1.0)))
+                return fail(TN_EINVAL, unif ? "rnd must hold uniforms in [0, 1]" : "rnd must be finite");
+    }
     prof_begin(&s->prof, TN_K_JUMPS, s->stream);
     // host copies of L (row-major 2x2 per channel) and L^+L for the closing kernels
     std::vector<double2> jl(4 * s->njump), jL(4 * s->njump);

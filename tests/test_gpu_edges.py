@@ -165,3 +165,38 @@ def test_exactly_degenerate_spectrum(prec):
         C_g, _ = measure.corr_mps(tebd.TNState(t3, l3, ln3), normalize=True)
         assert np.max(np.abs(C_g - C_o)) / np.max(np.abs(C_o)) < tol
     g.close()
+
+
+def test_host_rejects_non_finite_and_out_of_range_inputs():
+    """Inputs that would put NaN or Inf into the kernels are refused on the host with TN_EINVAL
+    before anything is launched, and the state stays usable."""
+    L, chi = 6, 8
+    bad = api.Model.free_fermion(L)
+    bad.h[2, 1, 1] = np.nan
+    with pytest.raises(api.TnError) as e:
+        api.State(api.KIND_MPS, bad, 2, chi, tn_inputs.neel(L))
+    assert e.value.code == api.TN_EINVAL
+    g = api.State(api.KIND_MPS, api.Model.free_fermion(L), 2, chi, tn_inputs.neel(L))
+    tensors, lams, _ = tn_inputs.random_isometric_mps(3, L, chi)
+    t_nan = [t.copy() for t in tensors]
+    t_nan[2][0, 0, 0] = np.inf
+    l_neg = [x.copy() for x in lams]
+    l_neg[1][0] = -0.5
+    for args in ((t_nan, lams, 0.0), (tensors, l_neg, 0.0), (tensors, lams, np.nan)):
+        with pytest.raises(api.TnError) as e:
+            g.set_instance(0, *args)
+        assert e.value.code == api.TN_EINVAL
+    for mode, rnd, kind in ((api.MODE_QT, np.array([0.5, 1.5]), api.NOISE_GAUSS),
+                            (api.MODE_QSD, np.full(2 * 2 * 2, np.nan), api.NOISE_GAUSS),
+                            (api.MODE_QSD, np.full(2 * 2, -0.1), api.NOISE_BINARY)):
+        with pytest.raises(api.TnError) as e:
+            g.apply_jumps(mode, 0.01, rnd, kind)
+        assert e.value.code == api.TN_EINVAL
+    with pytest.raises(api.TnError):
+        g.apply_jumps(api.MODE_QSD, -0.01, np.zeros(2 * 2 * 2), api.NOISE_GAUSS)
+    # the state is untouched and still steps
+    g.set_instance(0, tensors, lams, 0.0)
+    g.tebd_step(0.01)
+    C, _, _, _ = g.measure_corr()
+    assert np.all(np.isfinite(C))
+    g.close()
