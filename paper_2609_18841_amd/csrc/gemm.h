@@ -47,9 +47,16 @@ typedef double gemm_d4 __attribute__((ext_vector_type(4)));
 // added exactly, about sqrt(K / BK) times less than one K-deep FP32 accumulation.  The store
 // functor receives the FP64 sums.  Operand layouts: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; accumulator element r of lane l is C[4*(l/16) + r][l%16].
-template <bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
+// The store runs in PASSES passes over row halves (PASSES 2: waves 0-1 hold tile rows 0-31, waves
+// 2-3 rows 32-63); ep(pass) is called by every thread after each pass, so a kernel can stage half
+// the output tile in LDS at a time.
+struct NoEpilogue {
+    __device__ void operator()(int) const {}
+};
+
+template <bool A_KFAST, bool B_NFAST, int BK, int PASSES = 1, class LA, class LB, class SC, class EP = NoEpilogue>
 __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
-                                                    float2* As, float2* Bs) {
+                                                    float2* As, float2* Bs, EP ep = EP{}) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
@@ -100,15 +107,20 @@ __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0,
                     di[a][b][r] += (double)ci[a][b][r];
                 }
     }
+    for (int pass = 0; pass < PASSES; ++pass) {
+        if (PASSES == 1 || (wv >> 1) == pass) {  // uniform per wave
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * a + 4 * lk + r, gn = n0 + wn + 16 * b + li;
-                if (gm < M && gn < N) sc(gm, gn, make_double2(dr[a][b][r], di[a][b][r]));
-            }
+                    for (int r = 0; r < 4; ++r) {
+                        const int gm = m0 + wm + 16 * a + 4 * lk + r, gn = n0 + wn + 16 * b + li;
+                        if (gm < M && gn < N) sc(gm, gn, make_double2(dr[a][b][r], di[a][b][r]));
+                    }
+        }
+        ep(pass);
+    }
 }
 
 
@@ -116,9 +128,9 @@ __device__ __forceinline__ void block_gemm_mfma_c32(int M, int N, int K, int m0,
 // k-step of 4 is four real MFMA 16x16x4 f64 products per 16 x 16 block, accumulated in FP64.
 // Operand layouts as above (lane l supplies A[l%16][l/16] and B[l/16][l%16]); accumulator element
 // r of lane l is C[l/16 + 4*r][l%16].
-template <bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
+template <bool A_KFAST, bool B_NFAST, int BK, int PASSES = 1, class LA, class LB, class SC, class EP = NoEpilogue>
 __device__ __forceinline__ void block_gemm_mfma_c64(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
-                                                    double2* As, double2* Bs) {
+                                                    double2* As, double2* Bs, EP ep = EP{}) {
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
@@ -152,23 +164,29 @@ __device__ __forceinline__ void block_gemm_mfma_c64(int M, int N, int K, int m0,
         }
         __syncthreads();
     }
+    for (int pass = 0; pass < PASSES; ++pass) {
+        if (PASSES == 1 || (wv >> 1) == pass) {  // uniform per wave
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * a + lk + 4 * r, gn = n0 + wn + 16 * b + li;
-                if (gm < M && gn < N) sc(gm, gn, make_double2(cr[a][b][r], ci[a][b][r]));
-            }
+                    for (int r = 0; r < 4; ++r) {
+                        const int gm = m0 + wm + 16 * a + lk + 4 * r, gn = n0 + wn + 16 * b + li;
+                        if (gm < M && gn < N) sc(gm, gn, make_double2(cr[a][b][r], ci[a][b][r]));
+                    }
+        }
+        ep(pass);
+    }
 }
 
-template <class Acc, bool A_KFAST, bool B_NFAST, int BK, class LA, class LB, class SC>
+template <class Acc, bool A_KFAST, bool B_NFAST, int BK, int PASSES = 1, class LA, class LB, class SC,
+          class EP = NoEpilogue>
 __device__ __forceinline__ void block_gemm(int M, int N, int K, int m0, int n0, LA la, LB lb, SC sc,
-                                           Acc* As /* BK*64 */, Acc* Bs /* BK*64 */) {
+                                           Acc* As /* BK*64 */, Acc* Bs /* BK*64 */, EP ep = EP{}) {
     static_assert(BK % 4 == 0, "MFMA k-steps of 4");
     if constexpr (std::is_same<Acc, float2>::value)
-        block_gemm_mfma_c32<A_KFAST, B_NFAST, BK>(M, N, K, m0, n0, la, lb, sc, As, Bs);
+        block_gemm_mfma_c32<A_KFAST, B_NFAST, BK, PASSES>(M, N, K, m0, n0, la, lb, sc, As, Bs, ep);
     else
-        block_gemm_mfma_c64<A_KFAST, B_NFAST, BK>(M, N, K, m0, n0, la, lb, sc, As, Bs);
+        block_gemm_mfma_c64<A_KFAST, B_NFAST, BK, PASSES>(M, N, K, m0, n0, la, lb, sc, As, Bs, ep);
 }

@@ -90,10 +90,12 @@ __global__ __launch_bounds__(NT) void k_theta(DevState s, DevWork w, int tiles_n
 // mixes, rows (a, p) and columns (q, c), all land in one tile.  The tile is staged in LDS and
 // the gate applied on the way to memory.
 template <class T, class TC, int DM>
-__global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int tiles_n) {
-    // the output tile (FP64) reuses the operand staging space: block_gemm ends its k loop with a
-    // barrier, after which the staging buffers are dead
-    __shared__ double2 smem[64 * 64];
+__global__ __launch_bounds__(NT, DM <= 4 ? 4 : 2) void k_theta_gate(DevState s, DevWork w, int tiles_n) {
+    // Half of the output tile (32 rows, FP64) is staged at a time and reuses the operand staging
+    // space: block_gemm ends its k loop with a barrier, after which the staging buffers are dead.
+    // With 36 KB of LDS and, for d_l d_r <= 4, the launch bound (at most 128 registers, no spills)
+    // four workgroups share a CU (the whole tile in LDS allowed two).
+    __shared__ double2 smem[32 * 64];
     __shared__ double2 G[256];
     TC* As = reinterpret_cast<TC*>(smem);
     TC* Bs = As + 8 * 64;
@@ -116,35 +118,40 @@ __global__ __launch_bounds__(NT) void k_theta_gate(DevState s, DevWork w, int ti
     const T* Q = site_ptr<T>(s, d.b, d.bond + 1);
     double2* out = reinterpret_cast<double2*>(w.theta) + (size_t)blockIdx.y * w.theta_stride;
     const int K = d.chim, m0 = tm * 64;
-    block_gemm<TC, true, true, 8>(
+    // rows (a, p) of one pair never straddle the halves: 32 is a multiple of d_l (<= 8)
+    const auto gate_half = [&](int pass) {
+        __syncthreads();  // the half's entries are in LDS
+        const int h0 = m0 + 32 * pass;
+        const int npair = (32 / dl) * cw;
+        for (int e = threadIdx.x; e < npair; e += NT) {
+            const int al = e / cw, cl = e % cw, c = tn * cw + cl;
+            const int r0 = h0 + al * dl;
+            if (c >= chir || r0 >= d.m) continue;
+            double2 v[DM];
+#pragma unroll
+            for (int x = 0; x < DM; ++x)
+                if (x < D) v[x] = tile[(al * dl + x / dr) * 64 + (x % dr) * cw + cl];
+#pragma unroll
+            for (int o = 0; o < DM; ++o) {
+                if (o < D) {
+                    double2 acc = v[o];
+#pragma unroll
+                    for (int x = 0; x < DM; ++x)
+                        if (x < D) cfma(acc, G[o * D + x], v[x]);
+                    out[(size_t)(r0 + o / dr) * n + (o % dr) * chir + c] = acc;
+                }
+            }
+        }
+        __syncthreads();  // the half is consumed before the next one is stored
+    };
+    block_gemm<TC, true, true, 8, 2>(
         d.m, tiles_n * 64, K, m0, tn * 64,
         [&](int r, int k) { return cconv<TC>(P[(size_t)r * K + k]); },
         [&](int k, int V) {
             const int loc = V & 63, q = loc / cw, c = (V >> 6) * cw + loc % cw;
             return c < chir ? cconv<TC>(Q[(size_t)k * n + q * chir + c]) : czero<TC>();
         },
-        [&](int r, int V, double2 v) { tile[(r - m0) * 64 + (V & 63)] = v; }, As, Bs);
-    __syncthreads();
-    const int npair = (64 / dl) * cw;
-    for (int e = threadIdx.x; e < npair; e += NT) {
-        const int al = e / cw, cl = e % cw, c = tn * cw + cl;
-        const int r0 = m0 + al * dl;
-        if (c >= chir || r0 >= d.m) continue;
-        double2 v[DM];
-#pragma unroll
-        for (int x = 0; x < DM; ++x)
-            if (x < D) v[x] = tile[(al * dl + x / dr) * 64 + (x % dr) * cw + cl];
-#pragma unroll
-        for (int o = 0; o < DM; ++o) {
-            if (o < D) {
-                double2 acc = v[o];
-#pragma unroll
-                for (int x = 0; x < DM; ++x)
-                    if (x < D) cfma(acc, G[o * D + x], v[x]);
-                out[(size_t)(r0 + o / dr) * n + (o % dr) * chir + c] = acc;
-            }
-        }
-    }
+        [&](int r, int V, double2 v) { tile[((r - m0) & 31) * 64 + (V & 63)] = v; }, As, Bs, gate_half);
 }
 
 // ------------------------------------------------------------------ weighted Gram (FP64)
