@@ -270,9 +270,11 @@ int tn_buckets(void* s, int on, int parity, int* count, int* nmax, int* nbonds, 
 
 /* ---- graph replay --------------------------------------------------------- */
 
-/* tebd_step replays one captured HIP graph per Trotter order (all layers of one step, kernel
- * launches only) for unmasked steps while timing is off and the stream given to mps_alloc is a
- * created (non-null) stream; otherwise it launches eagerly.  Both give identical results.
+/* tebd_step replays one captured HIP graph per schedule, Trotter order and masking (all layers
+ * of one step, kernel launches only; a masked step reads the mask from a fixed arena slot that
+ * the call refills first, so one graph serves every mask) while timing is off and the stream
+ * given to mps_alloc is a created (non-null) stream; otherwise it launches eagerly.  Both give
+ * identical results.
  * on = 0 switches replay off and releases the captured graphs; on = 1 (the default) allows it.
  * Returns TN_OK or TN_EINVAL (null handle). */
 int tn_graph_enable(void* s, int on);

@@ -79,7 +79,7 @@ struct tn_state {
     bool slot_valid[2];
     Prof prof;
     // one captured Trotter step (all layers, unmasked) per schedule and order, replayed by tebd_step
-    hipGraphExec_t gexec[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    hipGraphExec_t gexec[2][3][2] = {};  // [schedule][order][masked]
     int schedule = TN_SCHED_LAYER;
     int use_graph = 1;
     // autotuner: Householder variant for n <= 128 chosen by timing on the state's own data
@@ -138,10 +138,11 @@ static int workspace_slots(int L, int B, int chunk) {
 static void drop_graphs(tn_state* s) {
     for (int sc = 0; sc < 2; ++sc)
         for (int o = 0; o < 3; ++o)
-            if (s->gexec[sc][o]) {
-                hipGraphExecDestroy(s->gexec[sc][o]);
-                s->gexec[sc][o] = nullptr;
-            }
+            for (int m = 0; m < 2; ++m)
+                if (s->gexec[sc][o][m]) {
+                    hipGraphExecDestroy(s->gexec[sc][o][m]);
+                    s->gexec[sc][o][m] = nullptr;
+                }
 }
 
 static inline size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1043,14 +1044,15 @@ extern "C" int tebd_step(void* h, double dt, int order, int n_steps, const unsig
         HIPCHK(hipMemcpyAsync(s->arena + s->lay.off_mask, mask, s->B, hipMemcpyHostToDevice, s->stream));
         mdev = reinterpret_cast<const unsigned char*>(s->arena + s->lay.off_mask);
     }
-    // Unmasked, untimed steps replay one captured graph of the step's layers (kernel launches
-    // only: no memset or copy nodes); gates live in fixed arena slots, so a new dt needs no
-    // re-capture.  The library's stream must be a created stream for capture.
-    if (s->use_graph && !mdev && !s->prof.on && s->stream != nullptr && n_steps > 0) {
-        hipGraphExec_t& gx = s->gexec[s->schedule][order];
+    // Untimed steps replay one captured graph of the step's layers per schedule, order and
+    // masking (kernel launches only: no memset or copy nodes).  Gates and the mask live in fixed
+    // arena slots that the copies above refill, so a new dt or mask needs no re-capture.  The
+    // library's stream must be a created stream for capture.
+    if (s->use_graph && !s->prof.on && s->stream != nullptr && n_steps > 0) {
+        hipGraphExec_t& gx = s->gexec[s->schedule][order][mdev ? 1 : 0];
         if (!gx) {
             HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-            const int crc = run_step(s, layers, nullptr);
+            const int crc = run_step(s, layers, mdev);
             hipGraph_t graph = nullptr;
             const hipError_t ce = hipStreamEndCapture(s->stream, &graph);
             if (crc) {

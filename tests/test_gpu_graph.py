@@ -37,7 +37,8 @@ def test_graph_replay_equals_eager(prec, order):
 
 
 def test_graph_replay_with_changing_dt_and_masked_steps():
-    """A new dt only rewrites the gate slots the graph reads; masked steps run eagerly."""
+    """A new dt only rewrites the gate slots the graph reads; masked steps replay a graph of their
+    own that reads the mask from its arena slot, with a different mask at every replay."""
     L, chi, B = 10, 16, 4
     occ = tn_inputs.neel(L)
     us = tn_inputs.uniforms(13, (6, B))
