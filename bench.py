@@ -599,7 +599,7 @@ def run_workload(args):
                                "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
     elif wl == "qt":
         L, chi, B, dt = 32, 64, 1024, 0.01
-        pre = 100 if args.pre < 0 else args.pre
+        pre = 400 if args.pre < 0 else args.pre  # t = 4 of the configuration's t <= 5
         st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
                        sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
@@ -616,7 +616,9 @@ def run_workload(args):
                 n_upd += int(B - mask.sum()) * (L - 1)
                 jumps[0] += int(mask.sum())
             return n_upd
-        qt_steps(0, pre)
+        for k0 in range(0, pre, 100):
+            qt_steps(k0, min(100, pre - k0))
+            print(f"# qt: untimed step {min(pre, k0 + 100)}", file=sys.stderr, flush=True)
         jumps[0] = 0
         v, n_upd = timed(lambda k: qt_steps(pre, k), args.steps)
         mids = np.array([st.dims(b)[L // 2] for b in range(B)])
@@ -628,7 +630,7 @@ def run_workload(args):
         st.close()
     elif wl == "qsd-wide":
         L, chi, B, dt, inner = 64, 32, 4096, 0.01, 10
-        pre = 100 if args.pre < 0 else args.pre
+        pre = 400 if args.pre < 0 else args.pre  # t = 4 of the configuration's t <= 5
         st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, tn_inputs.neel(L), precision=api.SPLIT,
                        sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
@@ -638,21 +640,23 @@ def run_workload(args):
         for k in range(pre):
             st.tebd_step(dt, order=1)
             st.apply_jumps(api.MODE_QSD, dt, nz[k], api.NOISE_GAUSS)
+            if k % 100 == 99:
+                print(f"# qsd-wide: untimed step {k + 1}", file=sys.stderr, flush=True)
 
         def intervals(k):
             for r in range(k):
                 run_interval(api, st, nz[pre + r * inner:pre + (r + 1) * inner], inner, dt)
             return k * inner * (L - 1) * B
         v, n_upd = timed(intervals, args.steps)
-        mids = np.array([st.dims(b)[L // 2] for b in range(0, B, 64)])
+        mids = np.array([st.dims(b)[L // 2] for b in range(0, B, 16)])
         res.update({"metric": "two-site updates/s, QSD B=4096 L=64 chi<=32", "value": v, "updates": n_upd,
-                    "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max())},
+                    "middle_bond_dim": {"min": int(mids.min()), "max": int(mids.max()), "mean": float(mids.mean())},
                     "config": {"B": B, "L": L, "chi": chi, "dt": dt, "inner_steps": inner, "untimed_steps": pre,
                                "timed_intervals": args.steps, "start": "Neel", "theta_bits": args.theta_bits, "buckets": not args.no_buckets}})
         st.close()
     else:
         L, chi, chik, dt = 32, 64, 4, 0.02
-        pre = 100 if args.pre < 0 else args.pre
+        pre = 200 if args.pre < 0 else args.pre  # t = 4 of the configuration's t <= 5
         st = api.State(api.KIND_PURIFIED, api.Model.free_fermion(L), 1, chi, tn_inputs.neel(L), chi_k_max=chik,
                        precision=api.SPLIT, sv_cutoff=SV_CUTOFF["split"])
         st.theta_precision(args.theta_bits)
@@ -664,7 +668,9 @@ def run_workload(args):
                 st.tebd_step(dt, order=1)
                 st.apply_jumps(api.MODE_KRAUS, dt)
             return k * (L - 1)
-        psteps(pre)
+        for k0 in range(0, pre, 50):
+            psteps(min(50, pre - k0))
+            print(f"# purified: untimed step {min(pre, k0 + 50)}", file=sys.stderr, flush=True)
         v, n_upd = timed(psteps, args.steps)
         C, _, _, _ = st.measure_corr()
         ev = np.linalg.eigvalsh((C + C.conj().T) / 2)
