@@ -396,3 +396,38 @@ def test_checkpoint_resume_equals_continuous_run():
     Ca, _, _, na = a.measure_corr(normalize=0)
     Cb, _, _, nb = b.measure_corr(normalize=0)
     assert np.array_equal(Ca, Cb) and np.array_equal(na, nb)
+
+
+def test_qt_split_jump_decisions_agree_with_fp64():
+    """Configuration 4 at L = 64 (B = 256, chi <= 32, t = 1): the split path's QT jump decisions
+    against the FP64 path's on the same uniforms, draw by draw.  A decision can flip only when its
+    uniform lies within the split path's rounding (about 1e-7 relative) of a threshold, so the
+    agreement rate over all 25 600 (history, step) draws is reported and must exceed 99.9 %; a
+    history whose decision flipped continues from a different state, so its later draws count as
+    disagreeing too.  The split ensemble's densities stay within 4 sigma plus the O(dt) splitting
+    bias of the exact solution (eq. ErrorCLT)."""
+    L, chi, B, dt, n = 64, 32, 256, 0.01, 100
+    occ = tn_inputs.neel(L)
+    us = tn_inputs.uniforms(21, (n, B))
+    dec, Cs = [], []
+    for prec in (api.SPLIT, api.FP64):
+        st = api.State(api.KIND_MPS, api.Model.free_fermion(L), B, chi, occ, precision=prec, sv_cutoff=1e-6)
+        d = np.zeros((n, B), dtype=np.int32)
+        for k in range(n):
+            jumped, mask = st.apply_jumps(api.MODE_QT, dt, us[k])
+            d[k] = jumped
+            st.tebd_step(dt, order=1, mask=mask)
+        _, _, C_each, _ = st.measure_corr(normalize=1, each=True)
+        dec.append(d)
+        Cs.append(C_each)
+        st.close()
+    first_diff = np.where((dec[0] != dec[1]).any(0), (dec[0] != dec[1]).argmax(0), n)
+    agree = float(np.sum(np.minimum(first_diff, n))) / (n * B)
+    print(f"QT jump decisions, split vs FP64: {agree:.6f} agree; {int(np.sum(dec[1] >= 0))} jumps; "
+          f"{int(np.sum(first_diff < n))} histories diverged")
+    assert int(np.sum(dec[1] >= 0)) > 50  # the draws exercise the jumps
+    assert agree > 0.999
+    dens = np.real(np.einsum("bii->bi", Cs[0]))
+    mean, err = dens.mean(0), dens.std(0, ddof=1) / np.sqrt(B)
+    ne = np.real(np.diag(exact.c_exact(n * dt, occ)))
+    assert np.all(np.abs(mean - ne) < 4 * err + 0.01)
