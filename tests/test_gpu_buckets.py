@@ -151,3 +151,13 @@ def test_bucketed_mpdo_across_the_order_128_boundary_matches_oracle():
     C_o = measure.corr_mpdo(st)[0]
     assert np.max(np.abs(C_g - C_o)) < 1e-5
     g.close()
+
+
+def test_bucket_switch_rejects_bad_arguments():
+    st = api.State(api.KIND_MPS, api.Model.free_fermion(8), 2, 16, [0] * 8)
+    for on, parity in ((3, 0), (-2, 0), (1, 2), (1, -1)):
+        with pytest.raises(api.TnError) as e:
+            st.buckets(on=on, parity=parity)
+        assert e.value.code == api.TN_EINVAL
+    assert st.buckets(parity=1) == st.buckets(on=-1, parity=1)
+    st.close()
