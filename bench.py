@@ -206,6 +206,8 @@ def parse():
                          "roofline line only (for rocprofv3 runs, whose traces then hold one-stream dispatches)")
     ap.add_argument("--summarize-trace", default="", metavar="DIR",
                     help="print the per-kernel summary of a rocprofv3 --stats --output-format csv run and exit")
+    ap.add_argument("--summarize-counters", default="",
+                    help="print the per-kernel means of a rocprofv3 --pmc run's counters and exit")
     ap.add_argument("--summarize-pmc", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="print the per-kernel HBM traffic from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of "
@@ -267,6 +269,27 @@ def _pmc_means(directory, counter, counts=False):
         a[1] += 1
     means = {k: v / n for k, (v, n) in acc.items()}
     return (means, {k: n for k, (_, n) in acc.items()}) if counts else means
+
+
+def summarize_counters(directory):
+    """Per-kernel mean of every counter of a rocprofv3 --pmc run, per dispatch, with the number of
+    dispatches (kernels by total of the first counter)."""
+    acc = {}
+    names = []
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        c = r.get("Counter_Name")
+        if c not in names:
+            names.append(c)
+        a = acc.setdefault(r["Kernel_Name"], {}).setdefault(c, [0.0, 0])
+        a[0] += float(r["Counter_Value"])
+        a[1] += 1
+    lines = [f"{'kernel':60s} {'dispatches':>10s} " + " ".join(f"{c:>26s}" for c in names)]
+    first = names[0] if names else None
+    for k in sorted(acc, key=lambda k: -acc[k].get(first, [0.0, 1])[0]):
+        n = max(v[1] for v in acc[k].values())
+        vals = " ".join(f"{(acc[k][c][0] / acc[k][c][1]) if c in acc[k] else 0.0:26.4e}" for c in names)
+        lines.append(f"{k[:60]:60s} {n:10d} {vals}")
+    return lines
 
 
 def summarize_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib=1024):
@@ -692,6 +715,9 @@ def main():
         return
     if args.summarize_pmc:
         print("\n".join(summarize_pmc(*args.summarize_pmc)))
+        return
+    if args.summarize_counters:
+        print("\n".join(summarize_counters(args.summarize_counters)))
         return
     if args.workload != "qsd":
         run_workload(args)
